@@ -1,0 +1,316 @@
+/*
+ * bits.h -- C ABI of libbits.so: Binary Interval Search (BITS) on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Layer, Skadron, Robins, Hall, Quinlan, "Binary Interval Search
+ * (BITS): A Scalable Algorithm for Counting Interval Intersections",
+ * Bioinformatics 2012.  Section/algorithm references below are to that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Intervals are closed, 0-based uint32 coordinates [start, end] with
+ *    start <= end (Sec. 1.1: a and b intersect when a.start <= b.end and
+ *    a.end >= b.start).  Sets are passed as two arrays (structure of arrays).
+ *  - Pointers prefixed d_ (and every array argument unless marked "host") are
+ *    DEVICE pointers on the current HIP device, owned by the caller.  The
+ *    library never allocates device memory in these calls: scratch comes
+ *    from caller-provided workspaces sized by the *_workspace functions.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Every
+ *    compute call only enqueues work on it and returns; results are valid
+ *    once the stream has reached that point.  Calls on one stream are
+ *    ordered; two streams must not write the same outputs concurrently.
+ *  - Return value: a bits_status.  Host-detectable argument errors return
+ *    immediately without enqueuing anything.  Errors found while the kernels
+ *    run (an interval with start > end, an interval that leaves its
+ *    chromosome) set bits in a device status word, read by bits_get_status.
+ *    Nothing aborts or throws across this boundary.
+ *  - Counts are exact integers: per-query counts uint32 (<= |B| < 2^32),
+ *    totals uint64.
+ */
+#ifndef BITS_H
+#define BITS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bits_status {
+    BITS_OK = 0,
+    BITS_E_ARG = 1,          /* null pointer with n > 0, size or parameter out of range */
+    BITS_E_INTERVAL = 2,     /* an interval with start > end (device-detected) */
+    BITS_E_CHROM = 3,        /* an interval outside its chromosome, or genome >= 2^32 */
+    BITS_E_WORKSPACE = 4,    /* caller buffer smaller than the *_workspace/_bytes size */
+    BITS_E_HIP = 5,          /* a HIP runtime call failed */
+    BITS_E_UNSUPPORTED = 6   /* no usable gfx950 device */
+} bits_status;
+
+/* Device status-word bits (OR-ed by kernels). */
+#define BITS_FLAG_INTERVAL 0x1u   /* start > end seen */
+#define BITS_FLAG_CHROM    0x2u   /* interval outside its chromosome */
+
+#define BITS_MAX_CHROM   256u     /* chromosomes per genome for projection / Monte-Carlo */
+#define BITS_MAX_DEPTH   13u      /* Eytzinger top-tree levels held in LDS */
+#define BITS_RMI_LEAVES  4096u    /* leaf models per learned index */
+#define BITS_RMI_HIDDEN  16u      /* hidden ReLU units per leaf model */
+#define BITS_RMI_PARAMS  49u      /* w1[16], b1[16], w2[16], b2 */
+
+/* Search path selection for a call (bits_launch.path). */
+#define BITS_PATH_AUTO    0u      /* learned index if the reference has one, else plain */
+#define BITS_PATH_PLAIN   1u      /* LDS Eytzinger top tree + bisection in HBM */
+#define BITS_PATH_LEARNED 2u      /* learned CDF index + windowed search (needs learned ref) */
+
+/* Launch shape of the search kernels.  A NULL bits_launch* means the
+ * library defaults; bits_autotune_count picks one by timing. */
+typedef struct bits_launch {
+    uint32_t block;   /* threads per workgroup: 256, 512 or 1024 (0 = default 1024) */
+    uint32_t qpl;     /* queries interleaved per lane: 1, 2 or 4 (0 = default 2) */
+    uint32_t depth;   /* top-tree levels searched from LDS, <= the reference's depth
+                         (0xFFFFFFFF = the reference's depth; 0 = no LDS tree) */
+    uint32_t grid;    /* workgroups, 0 = one persistent wave of workgroups per CU slot */
+    uint32_t path;    /* BITS_PATH_* */
+} bits_launch;
+
+/* Reference (database) index over B.  Filled by bits_ref_init from ONE
+ * caller-allocated device block; every pointer below points into it.
+ * Layout of the block (each region 256-byte aligned):
+ *   status[64]   uint32: [0] status bits, [2..3] uint64 learned-path fallbacks
+ *   tree         uint32[2][2^depth]: Eytzinger splitters of B_S then B_E,
+ *                node k (1-based BFS order) at [k]; entry 0 unused
+ *   rmi          (learned only) 2 x bits_rmi_model
+ *   bs, be       uint32[n] each: sorted B_S and B_E (Sec. 2.1, Algorithm 2) */
+typedef struct bits_ref {
+    uint64_t n;          /* |B|, < 2^32 */
+    uint32_t depth;      /* top-tree depth built: min(requested, floor(log2 n)) */
+    uint32_t learned;    /* 1 if the learned CDF index is present */
+    uint32_t *bs;        /* device: sorted starts */
+    uint32_t *be;        /* device: sorted ends */
+    uint32_t *tree;      /* device: 2 * 2^depth splitters */
+    void *rmi;           /* device: 2 bits_rmi_model (starts, ends) or NULL */
+    uint32_t *status;    /* device: status word and counters */
+    void *block;         /* device: base of the caller's block */
+    size_t block_bytes;
+} bits_ref;
+
+/* One leaf of the learned CDF index (device layout, 256 bytes).  Keys routed
+ * to the leaf are the contiguous sorted range [rlo, rlo + cnt). */
+typedef struct bits_rmi_leaf {
+    uint32_t kmin, kmax;     /* smallest / largest key of the leaf (kmin = 0xFFFFFFFF if empty) */
+    uint32_t rlo, cnt;       /* first rank and number of keys */
+    float kinv;              /* 1 / max(1, kmax - kmin) */
+    int32_t err_lo, err_hi;  /* max over-/under-prediction of the rank over the leaf's keys */
+    float loss;              /* final training loss (mean squared, normalised ranks) */
+    float p[BITS_RMI_PARAMS];/* w1[16], b1[16], w2[16], b2 */
+    uint32_t pad[7];
+} bits_rmi_leaf;
+
+/* Learned CDF index of one sorted array: root line routing to 4096 leaves. */
+typedef struct bits_rmi_model {
+    float root_a, root_b;    /* leaf = clamp(floor(fmaf(root_a, (float)x, root_b)), 0, 4095) */
+    double fit_a, fit_b;     /* least-squares line rank ~ fit_a * key + fit_b (fp64) */
+    uint64_t n;
+    uint32_t pad[56];
+    bits_rmi_leaf leaf[BITS_RMI_LEAVES];
+} bits_rmi_model;
+
+/* Training settings for the learned index (NULL = defaults). */
+typedef struct bits_train {
+    uint32_t epochs;      /* full-batch Adam steps per leaf (default 300; 0 = init only) */
+    uint32_t max_points;  /* training points per leaf, stride-sampled (default 4096, <= 4096) */
+    float lr;             /* Adam step size (default 2e-3) */
+    float beta1, beta2;   /* Adam moments (defaults 0.9, 0.999) */
+} bits_train;
+
+/* Summary of a learned index (host-side result of bits_rmi_info). */
+typedef struct bits_rmi_stats {
+    double mean_window;      /* mean err_lo + err_hi + 1 over non-empty leaves, both arrays */
+    uint32_t max_window;
+    uint32_t empty_leaves;
+    double mean_loss;
+    uint64_t fallbacks;      /* queries whose window failed verification since the last reset */
+} bits_rmi_stats;
+
+/* ---------------------------------------------------------------------- */
+/* Library                                                                 */
+/* ---------------------------------------------------------------------- */
+
+/* ABI version (monotone integer). */
+int bits_version(void);
+
+/* Human-readable name of a bits_status. Never NULL. */
+const char *bits_strerror(int status);
+
+/* Waits for `stream`, then copies the device status word d_status (4 bytes)
+ * into *status_out (BITS_FLAG_* bits).  Returns BITS_E_HIP on a runtime error. */
+int bits_get_status(const uint32_t *d_status, void *stream, uint32_t *status_out);
+
+/* Enqueues a zero fill of the device status word. */
+int bits_clear_status(uint32_t *d_status, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Projection (Sec. 2.1, "BITS solution to the counting problem"; Sec. 3.2) */
+/* ---------------------------------------------------------------------- */
+
+/* Maps chromosome-local intervals to the one-dimensional genome: global =
+ * (sum of the lengths of chromosomes before c) + local.
+ *   chrom_len  host, n_chrom lengths (n_chrom <= BITS_MAX_CHROM, sum < 2^32)
+ *   d_chrom, d_lstart, d_lend   device, n each: chromosome id, local closed interval
+ *   d_start, d_end              device, n each: output global interval
+ *   d_status   device status word (nullable): BITS_FLAG_CHROM for a bad id or
+ *              an interval past its chromosome's end, BITS_FLAG_INTERVAL for
+ *              start > end.  Such intervals are written as given. */
+int bits_project(const uint32_t *chrom_len, uint32_t n_chrom, const uint32_t *d_chrom,
+                 const uint32_t *d_lstart, const uint32_t *d_lend, uint64_t n,
+                 uint32_t *d_start, uint32_t *d_end, uint32_t *d_status, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Reference index: sort (Algorithm 2), top tree, learned CDF model         */
+/* ---------------------------------------------------------------------- */
+
+/* Bytes of the device block for a reference of n intervals. */
+int bits_ref_bytes(uint64_t n, uint32_t depth, int learned, size_t *bytes);
+
+/* Host only: carves the caller's device block (at least bits_ref_bytes) into
+ * *ref.  depth is clamped to min(depth, BITS_MAX_DEPTH, floor(log2 n)). */
+int bits_ref_init(void *d_block, size_t block_bytes, uint64_t n, uint32_t depth, int learned,
+                  bits_ref *ref);
+
+/* Workspace bytes bits_sort_ref needs for n intervals. */
+int bits_sort_ref_workspace(uint64_t n, size_t *bytes);
+
+/* Builds the reference index from B (Algorithm 2's setup): B_S and B_E are
+ * sorted ascending by an on-device LSD radix sort (8-bit digits, digits
+ * constant over the whole input skipped), the Eytzinger top tree of each is
+ * built, and if ref->learned the learned CDF index is trained on the device
+ * and its per-leaf error windows measured.  Clears the status word.
+ *   d_b_start, d_b_end  device, ref->n each, unsorted (not modified)
+ *   d_ws, ws_bytes      device workspace >= bits_sort_ref_workspace(n)
+ *   train               host, NULL for defaults (ignored if not learned)
+ * The intervals' start <= end is not checked here (starts and ends are sorted
+ * independently); count calls check their queries. */
+int bits_sort_ref(const uint32_t *d_b_start, const uint32_t *d_b_end, const bits_ref *ref,
+                  void *d_ws, size_t ws_bytes, const bits_train *train, void *stream);
+
+/* Several references in one segmented sort: refs[j] (host array) each with
+ * its own block, inputs d_b_start[j], d_b_end[j] (host arrays of device
+ * pointers).  Same semantics as bits_sort_ref for each j. */
+int bits_sort_refs_workspace(const uint64_t *n, uint32_t n_ref, size_t *bytes);
+int bits_sort_refs(const uint32_t *const *d_b_start, const uint32_t *const *d_b_end,
+                   const bits_ref *refs, uint32_t n_ref, void *d_ws, size_t ws_bytes,
+                   const bits_train *train, void *stream);
+
+/* Waits for `stream` and summarises the learned index of ref into *out. */
+int bits_rmi_info(const bits_ref *ref, void *stream, bits_rmi_stats *out);
+
+/* ---------------------------------------------------------------------- */
+/* Counting (Algorithm 1 ICount; Algorithm 2 Counter; Sec. 2.3)            */
+/* ---------------------------------------------------------------------- */
+
+/* Per-interval counting sub-problem (Sec. 1.1, problem 3): for each query
+ * a_i, d_counts[i] = |{b in B : a_i.start <= b.end and a_i.end >= b.start}|
+ * = upper_bound(B_S, a_i.end) - lower_bound(B_E, a_i.start).
+ *   d_a_start, d_a_end  device, na each
+ *   d_counts            device, na uint32, in query order
+ *   d_total             device uint64 (nullable): sum of the counts (overwritten)
+ *   launch              host, NULL for defaults
+ * A query with start > end sets BITS_FLAG_INTERVAL in ref->status and counts 0. */
+int bits_count_per_query(const bits_ref *ref, const uint32_t *d_a_start, const uint32_t *d_a_end,
+                         uint64_t na, uint32_t *d_counts, uint64_t *d_total,
+                         const bits_launch *launch, void *stream);
+
+/* Counting sub-problem (Sec. 1.1, problem 2; Algorithm 2): *d_total = sum of
+ * the per-query counts, exact uint64 (overwritten). */
+int bits_count(const bits_ref *ref, const uint32_t *d_a_start, const uint32_t *d_a_end,
+               uint64_t na, uint64_t *d_total, const bits_launch *launch, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Monte-Carlo significance (Sec. 3.2)                                      */
+/* ---------------------------------------------------------------------- */
+
+/* Workspace bytes bits_mc_pvalue needs for na queries. */
+int bits_mc_workspace(uint64_t na, size_t *bytes);
+
+/* Shuffles the query set A against the fixed reference and counts, in one
+ * persistent launch over all shuffles [s0, s1).  Shuffle s places query i at
+ * a uniformly drawn legal start of its own chromosome, length kept:
+ *   g = s * na + i;  (x0,x1,x2,x3) = Philox4x32-10(counter = (lo32 g, hi32 g, 0, 0),
+ *                                                  key = (lo32 seed, hi32 seed))
+ *   local = floor(((x1 << 32) | x0) * span / 2^64),  span = len_c - L + 1
+ *   a'    = [off_c + local, off_c + local + L - 1]
+ * (Philox-4x32-10: Salmon et al., SC'11.)
+ *   chrom_len        host, n_chrom lengths of the genome A was projected on;
+ *                    a query's chromosome is the one holding its start
+ *   d_totals         device uint64[s1 - s0]: per-shuffle totals
+ *   d_observed       device uint64: total of the unshuffled A
+ *   d_n_ge, d_n_le   device uint64: #{s : T_s >= T_obs}, #{s : T_s <= T_obs}
+ * The one-sided empirical p-value is bits_pvalue(n_ge, s1 - s0).  A query
+ * outside its chromosome sets BITS_FLAG_CHROM and is left out of every total. */
+int bits_mc_pvalue(const bits_ref *ref, const uint32_t *d_a_start, const uint32_t *d_a_end,
+                   uint64_t na, const uint32_t *chrom_len, uint32_t n_chrom, uint64_t seed,
+                   uint64_t s0, uint64_t s1, void *d_ws, size_t ws_bytes, uint64_t *d_totals,
+                   uint64_t *d_observed, uint64_t *d_n_ge, uint64_t *d_n_le,
+                   const bits_launch *launch, void *stream);
+
+/* (1 + n_ge) / (n_shuffles + 1) as one IEEE fp64 division (host). */
+double bits_pvalue(uint64_t n_ge, uint64_t n_shuffles);
+
+/* ---------------------------------------------------------------------- */
+/* Batched pairs: many query sets x many references, one persistent launch  */
+/* captured in a HIP graph (the many-pairs screen of Sec. 3.3).             */
+/* ---------------------------------------------------------------------- */
+
+typedef struct bits_batch_plan bits_batch_plan;   /* opaque host object */
+
+/* Workspace bytes for a plan over n_q query sets of sizes na[] (host). */
+int bits_batch_workspace(const uint64_t *na, uint32_t n_q, uint32_t n_ref, size_t *bytes);
+
+/* Builds a plan that computes d_pair_totals[i * n_ref + j] = total count of
+ * query set i against reference j for all pairs, as one zero-fill kernel and
+ * one persistent kernel captured into a HIP graph.  Work items (pair, tile)
+ * are ordered by reference so a workgroup re-stages the LDS top tree only
+ * when its reference changes.  Uploads the work list into d_ws (synchronous
+ * on `stream`).  refs and the query pointers are host arrays; the device
+ * buffers they name must stay valid while the plan is used. */
+int bits_batch_create(const bits_ref *refs, uint32_t n_ref, const uint32_t *const *d_a_start,
+                      const uint32_t *const *d_a_end, const uint64_t *na, uint32_t n_q,
+                      uint64_t *d_pair_totals, void *d_ws, size_t ws_bytes,
+                      const bits_launch *launch, void *stream, bits_batch_plan **plan);
+
+/* Replays the captured graph on `stream`. */
+int bits_batch_run(bits_batch_plan *plan, void *stream);
+
+/* Frees the host plan and its graph. */
+int bits_batch_destroy(bits_batch_plan *plan);
+
+/* ---------------------------------------------------------------------- */
+/* Autotuner                                                               */
+/* ---------------------------------------------------------------------- */
+
+/* Times bits_count on the given queries for every candidate launch shape
+ * (block 256/512/1024, qpl 1/2/4, LDS depth 8..ref->depth, the given path)
+ * with HIP events and writes the fastest to *best and its time to *best_ms.
+ * `path` is BITS_PATH_PLAIN or BITS_PATH_LEARNED.  Writes d_total. */
+int bits_autotune_count(const bits_ref *ref, const uint32_t *d_a_start, const uint32_t *d_a_end,
+                        uint64_t na, uint64_t *d_total, uint32_t path, bits_launch *best,
+                        float *best_ms, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Learned-model gradient (exposes the training kernel's own device code)   */
+/* ---------------------------------------------------------------------- */
+
+/* Loss and gradient of one leaf model over m points, computed by the same
+ * device code the training kernel runs (fp32):
+ *   loss = mean_i (y(u_i) - t_i)^2,  y(u) = b2 + sum_j w2_j relu(w1_j u + b1_j)
+ *   d_u, d_t      device float[m], m <= 4096
+ *   d_params      device float[49]  (w1[16], b1[16], w2[16], b2)
+ *   d_grad        device float[49];  d_loss device float[1] */
+int bits_rmi_leaf_grad(const float *d_u, const float *d_t, uint32_t m, const float *d_params,
+                       float *d_grad, float *d_loss, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BITS_H */

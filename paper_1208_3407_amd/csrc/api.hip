@@ -1,0 +1,591 @@
+// C ABI of libbits.so: argument checks, workspace carving and launch
+// sequencing for the entry points declared in include/bits.h.  No entry
+// point allocates device memory; every call only enqueues work on the
+// caller's stream (bits_batch_create and the *_info/status readers, which
+// wait on it, excepted).
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "bits_internal.hpp"
+
+using namespace bits;
+
+namespace {
+
+constexpr size_t kStatusBytes = 256;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+uint32_t clamp_depth(uint64_t n, uint32_t depth) {
+    if (n == 0) return 0;
+    uint32_t lg = 0;
+    while (lg < 63 && (2ull << lg) <= n) ++lg;   // floor(log2 n)
+    uint32_t d = depth < BITS_MAX_DEPTH ? depth : BITS_MAX_DEPTH;
+    return d < lg ? d : lg;
+}
+
+struct RefLayout {
+    size_t status, tree, rmi, bs, be, total;
+};
+
+RefLayout ref_layout(uint64_t n, uint32_t depth, int learned) {
+    RefLayout L;
+    size_t o = 0;
+    L.status = o; o = align256(o + kStatusBytes);
+    L.tree = o; o = align256(o + (size_t)2 * ((size_t)1 << depth) * sizeof(uint32_t));
+    L.rmi = o; o = align256(o + (learned ? 2 * sizeof(bits_rmi_model) : 0));
+    L.bs = o; o = align256(o + (size_t)n * sizeof(uint32_t));
+    L.be = o; o = align256(o + (size_t)n * sizeof(uint32_t));
+    L.total = o;
+    return L;
+}
+
+bool ref_ok(const bits_ref* r) {
+    if (!r || !r->status || !r->tree || r->n > 0xFFFFFFFFull) return false;
+    if (r->n && (!r->bs || !r->be)) return false;
+    if (r->learned && !r->rmi) return false;
+    return r->depth <= BITS_MAX_DEPTH;
+}
+
+bits_train train_defaults(const bits_train* t) {
+    bits_train d{300u, 4096u, 2e-3f, 0.9f, 0.999f};
+    if (!t) return d;
+    bits_train r = *t;
+    if (r.max_points == 0 || r.max_points > 4096) r.max_points = 4096;
+    if (!(r.lr > 0.0f)) r.lr = d.lr;
+    if (!(r.beta1 > 0.0f && r.beta1 < 1.0f)) r.beta1 = d.beta1;
+    if (!(r.beta2 > 0.0f && r.beta2 < 1.0f)) r.beta2 = d.beta2;
+    return r;
+}
+
+unsigned long long* fallback_counter(const bits_ref* r) {
+    return reinterpret_cast<unsigned long long*>(r->status + 2);
+}
+
+}  // namespace
+
+namespace bits {
+
+int resolve_launch(const bits_ref* ref, const bits_launch* in, LaunchCfg* out) {
+    LaunchCfg c{1024u, 2u, ref->depth, 0u, BITS_PATH_PLAIN};
+    if (in) {
+        if (in->block) c.block = in->block;
+        if (in->qpl) c.qpl = in->qpl;
+        if (in->depth != 0xFFFFFFFFu) c.depth = in->depth < ref->depth ? in->depth : ref->depth;
+        c.grid = in->grid;
+    }
+    const uint32_t path = in ? in->path : BITS_PATH_AUTO;
+    if (path == BITS_PATH_AUTO) c.path = ref->learned ? BITS_PATH_LEARNED : BITS_PATH_PLAIN;
+    else if (path == BITS_PATH_PLAIN || path == BITS_PATH_LEARNED) c.path = path;
+    else return BITS_E_ARG;
+    if (c.path == BITS_PATH_LEARNED && !ref->learned) return BITS_E_ARG;
+    if (c.block != 256 && c.block != 512 && c.block != 1024) return BITS_E_ARG;
+    if (c.qpl != 1 && c.qpl != 2 && c.qpl != 4) return BITS_E_ARG;
+    *out = c;
+    return BITS_OK;
+}
+
+SearchArgs make_search_args(const bits_ref* ref, const LaunchCfg& cfg) {
+    SearchArgs sa{};
+    sa.bs = ref->bs;
+    sa.be = ref->be;
+    sa.tree = ref->tree;
+    sa.rmi = (const bits_rmi_model*)ref->rmi;
+    sa.status = ref->status;
+    sa.fallbacks = fallback_counter(ref);
+    sa.n = (uint32_t)ref->n;
+    sa.tree_stride = 1u << ref->depth;
+    sa.depth = cfg.depth;
+    return sa;
+}
+
+int batch_blocks_per_cu(uint32_t qpl, uint32_t block, uint32_t max_depth);
+
+}  // namespace bits
+
+extern "C" {
+
+int bits_version(void) { return 1; }
+
+const char* bits_strerror(int status) {
+    switch (status) {
+        case BITS_OK: return "ok";
+        case BITS_E_ARG: return "invalid argument";
+        case BITS_E_INTERVAL: return "interval with start > end";
+        case BITS_E_CHROM: return "interval outside its chromosome or genome too large";
+        case BITS_E_WORKSPACE: return "workspace too small";
+        case BITS_E_HIP: return "HIP runtime error";
+        case BITS_E_UNSUPPORTED: return "unsupported device or parameter";
+        default: return "unknown status";
+    }
+}
+
+int bits_get_status(const uint32_t* d_status, void* stream, uint32_t* status_out) {
+    if (!d_status || !status_out) return BITS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    BITS_CHECK_HIP(hipStreamSynchronize(s));
+    uint32_t v = 0;
+    BITS_CHECK_HIP(hipMemcpy(&v, d_status, sizeof(v), hipMemcpyDeviceToHost));
+    *status_out = v;
+    return BITS_OK;
+}
+
+int bits_clear_status(uint32_t* d_status, void* stream) {
+    if (!d_status) return BITS_E_ARG;
+    BITS_CHECK_HIP(launch_fill_u32(d_status, 1, 0u, (hipStream_t)stream));
+    return BITS_OK;
+}
+
+int bits_project(const uint32_t* chrom_len, uint32_t n_chrom, const uint32_t* d_chrom, const uint32_t* d_lstart,
+                 const uint32_t* d_lend, uint64_t n, uint32_t* d_start, uint32_t* d_end, uint32_t* d_status,
+                 void* stream) {
+    if (!chrom_len || n_chrom == 0 || n_chrom > BITS_MAX_CHROM) return BITS_E_ARG;
+    if (n && (!d_chrom || !d_lstart || !d_lend || !d_start || !d_end)) return BITS_E_ARG;
+    uint64_t g = 0;
+    for (uint32_t c = 0; c < n_chrom; ++c) g += chrom_len[c];
+    if (g > 0xFFFFFFFFull) return BITS_E_CHROM;
+    BITS_CHECK_HIP(launch_project(chrom_len, n_chrom, d_chrom, d_lstart, d_lend, n, d_start, d_end, d_status,
+                                  (hipStream_t)stream));
+    return BITS_OK;
+}
+
+int bits_ref_bytes(uint64_t n, uint32_t depth, int learned, size_t* bytes) {
+    if (!bytes || n > 0xFFFFFFFFull) return BITS_E_ARG;
+    if (learned && n > 0x7FFFFFFFull) return BITS_E_ARG;
+    *bytes = ref_layout(n, clamp_depth(n, depth), learned).total;
+    return BITS_OK;
+}
+
+int bits_ref_init(void* d_block, size_t block_bytes, uint64_t n, uint32_t depth, int learned, bits_ref* ref) {
+    if (!d_block || !ref || n > 0xFFFFFFFFull) return BITS_E_ARG;
+    if (learned && n > 0x7FFFFFFFull) return BITS_E_ARG;
+    const uint32_t d = clamp_depth(n, depth);
+    const RefLayout L = ref_layout(n, d, learned);
+    if (block_bytes < L.total) return BITS_E_WORKSPACE;
+    if (((uintptr_t)d_block & 255u) != 0) return BITS_E_ARG;
+    char* b = (char*)d_block;
+    memset(ref, 0, sizeof(*ref));
+    ref->n = n;
+    ref->depth = d;
+    ref->learned = learned ? 1u : 0u;
+    ref->status = (uint32_t*)(b + L.status);
+    ref->tree = (uint32_t*)(b + L.tree);
+    ref->rmi = learned ? (void*)(b + L.rmi) : nullptr;
+    ref->bs = (uint32_t*)(b + L.bs);
+    ref->be = (uint32_t*)(b + L.be);
+    ref->block = d_block;
+    ref->block_bytes = block_bytes;
+    return BITS_OK;
+}
+
+int bits_sort_ref_workspace(uint64_t n, size_t* bytes) {
+    if (!bytes || n > 0xFFFFFFFFull) return BITS_E_ARG;
+    const uint64_t ns[2] = {n, n};
+    *bytes = std::max(sort_workspace_bytes(ns, 2), rmi_workspace_bytes());
+    return BITS_OK;
+}
+
+int bits_sort_refs_workspace(const uint64_t* n, uint32_t n_ref, size_t* bytes) {
+    if (!bytes || (n_ref && !n)) return BITS_E_ARG;
+    std::vector<uint64_t> ns(2 * (size_t)n_ref);
+    for (uint32_t j = 0; j < n_ref; ++j) {
+        if (n[j] > 0xFFFFFFFFull) return BITS_E_ARG;
+        ns[2 * j] = ns[2 * j + 1] = n[j];
+    }
+    *bytes = std::max(sort_workspace_bytes(ns.data(), 2 * n_ref), rmi_workspace_bytes());
+    return BITS_OK;
+}
+
+static int finish_ref(const bits_ref* r, const bits_train& tr, void* ws, hipStream_t s) {
+    BITS_CHECK_HIP(launch_fill_u32(r->status, kStatusBytes / 4, 0u, s));
+    if (r->n) {
+        BITS_CHECK_HIP(launch_build_tree(r->bs, r->n, r->depth, r->tree, s));
+        BITS_CHECK_HIP(launch_build_tree(r->be, r->n, r->depth, r->tree + ((size_t)1 << r->depth), s));
+    } else {
+        BITS_CHECK_HIP(launch_fill_u32(r->tree, (uint64_t)2 << r->depth, 0u, s));
+    }
+    if (r->learned) {
+        bits_rmi_model* m = (bits_rmi_model*)r->rmi;
+        if (r->n == 0) {
+            BITS_CHECK_HIP(launch_fill_u32((uint32_t*)m, 2 * sizeof(bits_rmi_model) / 4, 0u, s));
+        } else {
+            const int rc = launch_rmi_build2(r->bs, r->be, r->n, m, m + 1, tr, ws, s);
+            if (rc != BITS_OK) return rc;
+        }
+    }
+    return BITS_OK;
+}
+
+int bits_sort_ref(const uint32_t* d_b_start, const uint32_t* d_b_end, const bits_ref* ref, void* d_ws,
+                  size_t ws_bytes, const bits_train* train, void* stream) {
+    if (!ref_ok(ref)) return BITS_E_ARG;
+    if (ref->n && (!d_b_start || !d_b_end || !d_ws)) return BITS_E_ARG;
+    size_t need = 0;
+    bits_sort_ref_workspace(ref->n, &need);
+    if (ref->n && ws_bytes < need) return BITS_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (ref->n) {
+        SortSeg segs[2] = {{d_b_start, ref->bs, ref->n}, {d_b_end, ref->be, ref->n}};
+        const int rc = launch_sort(segs, 2, d_ws, ws_bytes, s);
+        if (rc != BITS_OK) return rc;
+    }
+    return finish_ref(ref, train_defaults(train), d_ws, s);
+}
+
+int bits_sort_refs(const uint32_t* const* d_b_start, const uint32_t* const* d_b_end, const bits_ref* refs,
+                   uint32_t n_ref, void* d_ws, size_t ws_bytes, const bits_train* train, void* stream) {
+    if (n_ref == 0) return BITS_OK;
+    if (!d_b_start || !d_b_end || !refs || !d_ws) return BITS_E_ARG;
+    std::vector<uint64_t> ns(n_ref);
+    std::vector<SortSeg> segs;
+    segs.reserve(2 * (size_t)n_ref);
+    for (uint32_t j = 0; j < n_ref; ++j) {
+        if (!ref_ok(&refs[j])) return BITS_E_ARG;
+        if (refs[j].n && (!d_b_start[j] || !d_b_end[j])) return BITS_E_ARG;
+        ns[j] = refs[j].n;
+        segs.push_back({d_b_start[j], refs[j].bs, refs[j].n});
+        segs.push_back({d_b_end[j], refs[j].be, refs[j].n});
+    }
+    size_t need = 0;
+    bits_sort_refs_workspace(ns.data(), n_ref, &need);
+    if (ws_bytes < need) return BITS_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = launch_sort(segs.data(), (uint32_t)segs.size(), d_ws, ws_bytes, s);
+    if (rc != BITS_OK) return rc;
+    const bits_train tr = train_defaults(train);
+    for (uint32_t j = 0; j < n_ref; ++j) {
+        rc = finish_ref(&refs[j], tr, d_ws, s);
+        if (rc != BITS_OK) return rc;
+    }
+    return BITS_OK;
+}
+
+int bits_rmi_info(const bits_ref* ref, void* stream, bits_rmi_stats* out) {
+    if (!ref_ok(ref) || !out || !ref->learned) return BITS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    BITS_CHECK_HIP(hipStreamSynchronize(s));
+    std::vector<bits_rmi_model> host(2);
+    BITS_CHECK_HIP(hipMemcpy(host.data(), ref->rmi, 2 * sizeof(bits_rmi_model), hipMemcpyDeviceToHost));
+    unsigned long long fb = 0;
+    BITS_CHECK_HIP(hipMemcpy(&fb, fallback_counter(ref), sizeof(fb), hipMemcpyDeviceToHost));
+    double wsum = 0.0, lsum = 0.0;
+    uint64_t nonempty = 0;
+    uint32_t wmax = 0, empty = 0;
+    for (int a = 0; a < 2; ++a)
+        for (uint32_t l = 0; l < BITS_RMI_LEAVES; ++l) {
+            const bits_rmi_leaf& L = host[a].leaf[l];
+            if (L.cnt == 0) {
+                ++empty;
+                continue;
+            }
+            const uint32_t w = (uint32_t)(L.err_lo + L.err_hi + 1);
+            wsum += w;
+            lsum += L.loss;
+            wmax = std::max(wmax, w);
+            ++nonempty;
+        }
+    out->mean_window = nonempty ? wsum / (double)nonempty : 0.0;
+    out->max_window = wmax;
+    out->empty_leaves = empty;
+    out->mean_loss = nonempty ? lsum / (double)nonempty : 0.0;
+    out->fallbacks = fb;
+    return BITS_OK;
+}
+
+static int check_queries(const bits_ref* ref, const uint32_t* as, const uint32_t* ae, uint64_t na) {
+    if (!ref_ok(ref)) return BITS_E_ARG;
+    if (na && (!as || !ae)) return BITS_E_ARG;
+    return BITS_OK;
+}
+
+int bits_count_per_query(const bits_ref* ref, const uint32_t* d_a_start, const uint32_t* d_a_end, uint64_t na,
+                         uint32_t* d_counts, uint64_t* d_total, const bits_launch* launch, void* stream) {
+    int rc = check_queries(ref, d_a_start, d_a_end, na);
+    if (rc != BITS_OK) return rc;
+    if (na && !d_counts) return BITS_E_ARG;
+    LaunchCfg cfg;
+    rc = resolve_launch(ref, launch, &cfg);
+    if (rc != BITS_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* tot = (unsigned long long*)d_total;
+    if (tot) BITS_CHECK_HIP(launch_fill_u64(tot, 1, 0ull, s));
+    if (ref->n == 0) {
+        BITS_CHECK_HIP(launch_fill_u32(d_counts, na, 0u, s));
+        return BITS_OK;
+    }
+    BITS_CHECK_HIP(launch_count(make_search_args(ref, cfg), cfg, d_a_start, d_a_end, na, d_counts, tot, s));
+    return BITS_OK;
+}
+
+int bits_count(const bits_ref* ref, const uint32_t* d_a_start, const uint32_t* d_a_end, uint64_t na,
+               uint64_t* d_total, const bits_launch* launch, void* stream) {
+    int rc = check_queries(ref, d_a_start, d_a_end, na);
+    if (rc != BITS_OK) return rc;
+    if (!d_total) return BITS_E_ARG;
+    LaunchCfg cfg;
+    rc = resolve_launch(ref, launch, &cfg);
+    if (rc != BITS_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* tot = (unsigned long long*)d_total;
+    BITS_CHECK_HIP(launch_fill_u64(tot, 1, 0ull, s));
+    if (ref->n == 0) return BITS_OK;
+    BITS_CHECK_HIP(launch_count(make_search_args(ref, cfg), cfg, d_a_start, d_a_end, na, nullptr, tot, s));
+    return BITS_OK;
+}
+
+int bits_mc_workspace(uint64_t na, size_t* bytes) {
+    if (!bytes) return BITS_E_ARG;
+    *bytes = 3 * align256((size_t)na * sizeof(uint32_t));
+    return BITS_OK;
+}
+
+int bits_mc_pvalue(const bits_ref* ref, const uint32_t* d_a_start, const uint32_t* d_a_end, uint64_t na,
+                   const uint32_t* chrom_len, uint32_t n_chrom, uint64_t seed, uint64_t s0, uint64_t s1,
+                   void* d_ws, size_t ws_bytes, uint64_t* d_totals, uint64_t* d_observed, uint64_t* d_n_ge,
+                   uint64_t* d_n_le, const bits_launch* launch, void* stream) {
+    int rc = check_queries(ref, d_a_start, d_a_end, na);
+    if (rc != BITS_OK) return rc;
+    if (s1 < s0 || !chrom_len || n_chrom == 0 || n_chrom > BITS_MAX_CHROM) return BITS_E_ARG;
+    if (!d_observed || !d_n_ge || !d_n_le || (s1 > s0 && !d_totals)) return BITS_E_ARG;
+    const uint64_t ns = s1 - s0;
+    if (na && ns > ~0ull / na) return BITS_E_ARG;   // counter g = s * na + i must not wrap
+    if (na && s1 > (~0ull - na) / na) return BITS_E_ARG;
+    uint64_t g = 0;
+    for (uint32_t c = 0; c < n_chrom; ++c) g += chrom_len[c];
+    if (g > 0xFFFFFFFFull) return BITS_E_CHROM;
+    size_t need = 0;
+    bits_mc_workspace(na, &need);
+    if (na && (!d_ws || ws_bytes < need)) return BITS_E_WORKSPACE;
+    LaunchCfg cfg;
+    rc = resolve_launch(ref, launch, &cfg);
+    if (rc != BITS_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    auto* totals = (unsigned long long*)d_totals;
+    auto* obs = (unsigned long long*)d_observed;
+    BITS_CHECK_HIP(launch_fill_u64(totals, ns, 0ull, s));
+    BITS_CHECK_HIP(launch_fill_u64(obs, 1, 0ull, s));
+    if (na && ref->n) {
+        const size_t stride = align256((size_t)na * sizeof(uint32_t));
+        uint32_t* off = (uint32_t*)d_ws;
+        uint32_t* span = (uint32_t*)((char*)d_ws + stride);
+        uint32_t* len = (uint32_t*)((char*)d_ws + 2 * stride);
+        BITS_CHECK_HIP(launch_mc_prepare(d_a_start, d_a_end, na, chrom_len, n_chrom, off, span, len, ref->status, s));
+        BITS_CHECK_HIP(launch_mc(make_search_args(ref, cfg), cfg, d_a_start, d_a_end, off, span, len, na, seed, s0,
+                                 ns, totals, obs, s));
+    }
+    BITS_CHECK_HIP(launch_mc_tail(totals, ns, obs, (unsigned long long*)d_n_ge, (unsigned long long*)d_n_le, s));
+    return BITS_OK;
+}
+
+double bits_pvalue(uint64_t n_ge, uint64_t n_shuffles) {
+    return (1.0 + (double)n_ge) / ((double)n_shuffles + 1.0);
+}
+
+// ---------------------------------------------------------------- batch
+
+struct bits_batch_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+struct BatchWs {
+    size_t refs, qs, items, wg, total;
+};
+BatchWs batch_ws(uint32_t n_ref, uint32_t n_q, uint64_t n_items, uint32_t n_wg) {
+    BatchWs w;
+    size_t o = 0;
+    w.refs = o; o = align256(o + sizeof(BatchRef) * n_ref);
+    w.qs = o; o = align256(o + sizeof(BatchQuery) * n_q);
+    w.items = o; o = align256(o + sizeof(BatchItem) * n_items);
+    w.wg = o; o = align256(o + sizeof(uint32_t) * ((size_t)n_wg + 1));
+    w.total = o;
+    return w;
+}
+constexpr uint32_t kMaxBatchWg = 256u * 16u;
+}  // namespace
+
+int bits_batch_workspace(const uint64_t* na, uint32_t n_q, uint32_t n_ref, size_t* bytes) {
+    if (!bytes || (n_q && !na)) return BITS_E_ARG;
+    uint64_t tiles = 0;
+    for (uint32_t i = 0; i < n_q; ++i) tiles += (na[i] + 255) / 256;   // smallest tile: 256 x 1
+    *bytes = batch_ws(n_ref, n_q, tiles * n_ref, kMaxBatchWg).total;
+    return BITS_OK;
+}
+
+int bits_batch_create(const bits_ref* refs, uint32_t n_ref, const uint32_t* const* d_a_start,
+                      const uint32_t* const* d_a_end, const uint64_t* na, uint32_t n_q, uint64_t* d_pair_totals,
+                      void* d_ws, size_t ws_bytes, const bits_launch* launch, void* stream, bits_batch_plan** plan) {
+    if (!plan || !refs || !d_a_start || !d_a_end || !na || !d_pair_totals || !d_ws || !n_ref || !n_q)
+        return BITS_E_ARG;
+    *plan = nullptr;
+    uint32_t max_depth = 0;
+    for (uint32_t j = 0; j < n_ref; ++j) {
+        if (!ref_ok(&refs[j])) return BITS_E_ARG;
+        max_depth = std::max(max_depth, refs[j].depth);
+    }
+    for (uint32_t i = 0; i < n_q; ++i) {
+        if (na[i] && (!d_a_start[i] || !d_a_end[i])) return BITS_E_ARG;
+        if (na[i] > 0xFFFFFFFFull) return BITS_E_ARG;
+    }
+    LaunchCfg cfg{1024u, 2u, max_depth, 0u, BITS_PATH_PLAIN};
+    if (launch) {
+        if (launch->block) cfg.block = launch->block;
+        if (launch->qpl) cfg.qpl = launch->qpl;
+        if (launch->depth != 0xFFFFFFFFu) cfg.depth = std::min(launch->depth, max_depth);
+        cfg.grid = launch->grid;
+        if (launch->path == BITS_PATH_LEARNED) return BITS_E_UNSUPPORTED;
+    }
+    if ((cfg.block != 256 && cfg.block != 512 && cfg.block != 1024) || (cfg.qpl != 1 && cfg.qpl != 2 && cfg.qpl != 4))
+        return BITS_E_ARG;
+    const uint32_t tile = cfg.block * cfg.qpl;
+
+    // Work list ordered by reference, then query set, then tile.
+    std::vector<BatchItem> items;
+    std::vector<double> cost;
+    for (uint32_t j = 0; j < n_ref; ++j) {
+        const double per_q = std::log2((double)refs[j].n + 2.0) + 8.0;
+        for (uint32_t i = 0; i < n_q; ++i)
+            for (uint64_t b = 0; b < na[i]; b += tile) {
+                const uint32_t c = (uint32_t)std::min<uint64_t>(tile, na[i] - b);
+                items.push_back({i, j, (uint32_t)b, c});
+                cost.push_back(c * per_q);
+            }
+    }
+    uint32_t n_wg = cfg.grid ? cfg.grid
+                             : (uint32_t)device_cu_count() * (uint32_t)batch_blocks_per_cu(cfg.qpl, cfg.block, cfg.depth);
+    n_wg = std::max(1u, std::min({n_wg, kMaxBatchWg, (uint32_t)std::max<size_t>(items.size(), 1)}));
+    const BatchWs W = batch_ws(n_ref, n_q, items.size(), n_wg);
+    if (ws_bytes < W.total) return BITS_E_WORKSPACE;
+    // Contiguous partition of the work list with near-equal cost per workgroup.
+    std::vector<uint32_t> wg(n_wg + 1, (uint32_t)items.size());
+    double total = 0.0;
+    for (double c : cost) total += c;
+    wg[0] = 0;
+    double acc = 0.0;
+    uint32_t w = 1;
+    for (size_t k = 0; k < items.size() && w < n_wg; ++k) {
+        acc += cost[k];
+        while (w < n_wg && acc >= total * w / n_wg) wg[w++] = (uint32_t)(k + 1);
+    }
+    std::vector<BatchRef> rtab(n_ref);
+    for (uint32_t j = 0; j < n_ref; ++j)
+        rtab[j] = {refs[j].bs, refs[j].be, refs[j].tree, (uint32_t)refs[j].n, 1u << refs[j].depth,
+                   std::min(refs[j].depth, cfg.depth), 0u};
+    std::vector<BatchQuery> qtab(n_q);
+    for (uint32_t i = 0; i < n_q; ++i) qtab[i] = {d_a_start[i], d_a_end[i], na[i]};
+    hipStream_t s = (hipStream_t)stream;
+    char* b = (char*)d_ws;
+    BITS_CHECK_HIP(hipMemcpyAsync(b + W.refs, rtab.data(), sizeof(BatchRef) * n_ref, hipMemcpyHostToDevice, s));
+    BITS_CHECK_HIP(hipMemcpyAsync(b + W.qs, qtab.data(), sizeof(BatchQuery) * n_q, hipMemcpyHostToDevice, s));
+    if (!items.empty())
+        BITS_CHECK_HIP(hipMemcpyAsync(b + W.items, items.data(), sizeof(BatchItem) * items.size(),
+                                      hipMemcpyHostToDevice, s));
+    BITS_CHECK_HIP(hipMemcpyAsync(b + W.wg, wg.data(), sizeof(uint32_t) * (n_wg + 1), hipMemcpyHostToDevice, s));
+    BITS_CHECK_HIP(hipStreamSynchronize(s));
+
+    bits_batch_plan* p = new (std::nothrow) bits_batch_plan();
+    if (!p) return BITS_E_ARG;
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        delete p;
+        return BITS_E_HIP;
+    }
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        ok = launch_fill_u64((unsigned long long*)d_pair_totals, (uint64_t)n_q * n_ref, 0ull, cs) == hipSuccess;
+        ok = ok && launch_batch((const BatchRef*)(b + W.refs), (const BatchQuery*)(b + W.qs),
+                                (const BatchItem*)(b + W.items), (const uint32_t*)(b + W.wg), n_wg, n_ref, cfg.depth,
+                                cfg, (unsigned long long*)d_pair_totals, refs[0].status, cs) == hipSuccess;
+        hipGraph_t g = nullptr;
+        const bool ended = hipStreamEndCapture(cs, &g) == hipSuccess;
+        ok = ok && ended && g;
+        p->graph = g;
+    }
+    if (ok) ok = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
+    (void)hipStreamDestroy(cs);
+    if (!ok) {
+        bits_batch_destroy(p);
+        return BITS_E_HIP;
+    }
+    *plan = p;
+    return BITS_OK;
+}
+
+int bits_batch_run(bits_batch_plan* plan, void* stream) {
+    if (!plan || !plan->exec) return BITS_E_ARG;
+    BITS_CHECK_HIP(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+    return BITS_OK;
+}
+
+int bits_batch_destroy(bits_batch_plan* plan) {
+    if (!plan) return BITS_OK;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
+    return BITS_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+
+int bits_autotune_count(const bits_ref* ref, const uint32_t* d_a_start, const uint32_t* d_a_end, uint64_t na,
+                        uint64_t* d_total, uint32_t path, bits_launch* best, float* best_ms, void* stream) {
+    int rc = check_queries(ref, d_a_start, d_a_end, na);
+    if (rc != BITS_OK) return rc;
+    if (!d_total || !best || !best_ms || (path != BITS_PATH_PLAIN && path != BITS_PATH_LEARNED)) return BITS_E_ARG;
+    if (path == BITS_PATH_LEARNED && !ref->learned) return BITS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<bits_launch> cand;
+    const uint32_t dmin = ref->depth > 8 ? 8 : ref->depth;
+    for (uint32_t block : {256u, 512u, 1024u})
+        for (uint32_t qpl : {1u, 2u, 4u}) {
+            if (path == BITS_PATH_LEARNED) {
+                cand.push_back({block, qpl, 0u, 0u, path});
+            } else {
+                for (uint32_t d = ref->depth + 1; d-- > dmin;) cand.push_back({block, qpl, d, 0u, path});
+            }
+        }
+    hipEvent_t e0, e1;
+    BITS_CHECK_HIP(hipEventCreate(&e0));
+    BITS_CHECK_HIP(hipEventCreate(&e1));
+    float bestt = 1e30f;
+    bits_launch bl = cand.front();
+    for (const bits_launch& c : cand) {
+        rc = bits_count(ref, d_a_start, d_a_end, na, d_total, &c, stream);   // warm-up
+        if (rc != BITS_OK) break;
+        float tmin = 1e30f;
+        for (int r = 0; r < 3; ++r) {
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = BITS_E_HIP; break; }
+            rc = bits_count(ref, d_a_start, d_a_end, na, d_total, &c, stream);
+            if (rc != BITS_OK) break;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = BITS_E_HIP; break; }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            tmin = std::min(tmin, ms);
+        }
+        if (rc != BITS_OK) break;
+        if (tmin < bestt) {
+            bestt = tmin;
+            bl = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != BITS_OK) return rc;
+    *best = bl;
+    *best_ms = bestt;
+    return BITS_OK;
+}
+
+int bits_rmi_leaf_grad(const float* d_u, const float* d_t, uint32_t m, const float* d_params, float* d_grad,
+                       float* d_loss, void* stream) {
+    if (m > 4096 || !d_params || !d_grad || !d_loss || (m && (!d_u || !d_t))) return BITS_E_ARG;
+    BITS_CHECK_HIP(launch_rmi_leaf_grad(d_u, d_t, m, d_params, d_grad, d_loss, (hipStream_t)stream));
+    return BITS_OK;
+}
+
+}  // extern "C"

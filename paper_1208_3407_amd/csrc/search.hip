@@ -1,0 +1,621 @@
+// Search kernels of libbits.so (gfx950): ICount (Algorithm 1) over the plain
+// index (LDS Eytzinger top tree + bisection of the bucket in HBM) or the
+// learned CDF index (route -> leaf model -> windowed bisection, verified),
+// the per-query / total counters (Algorithm 2), the Monte-Carlo loop of
+// Sec. 3.2 as one persistent launch, the batched-pairs kernel, projection and
+// small helpers.
+//
+// Every lane carries QPL queries, i.e. 2*QPL independent search chains (one
+// over B_S for a.end, one over B_E for a.start per query); the chains advance
+// in lock-step so their dependent loads overlap.
+#include <mutex>
+#include <unordered_map>
+
+#include "bits_internal.hpp"
+
+namespace bits {
+
+// ------------------------------------------------------------------ bisection
+// For each chain c: base[c] += #{K_c[base[c] .. base[c] + len[c]) < x[c]};
+// K_c is B_S for even c and B_E for odd c.  Leaves len[c] == 0.
+template <int NC>
+__device__ __forceinline__ void bisect_multi(const uint32_t* __restrict__ ks, const uint32_t* __restrict__ ke,
+                                             uint32_t (&base)[NC], uint32_t (&len)[NC], const uint32_t (&x)[NC]) {
+    while (true) {
+        uint32_t v[NC];
+        bool any = false;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const uint32_t* K = (c & 1) ? ke : ks;
+            const uint32_t half = len[c] >> 1;
+            v[c] = half ? K[base[c] + half - 1] : 0u;
+            any |= half != 0;
+        }
+        if (!any) break;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const uint32_t half = len[c] >> 1;
+            if (half) {
+                base[c] += (v[c] < x[c]) ? half : 0u;
+                len[c] -= half;
+            }
+        }
+    }
+    uint32_t v[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const uint32_t* K = (c & 1) ? ke : ks;
+        v[c] = len[c] ? K[base[c]] : 0u;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (len[c]) base[c] += (v[c] < x[c]) ? 1u : 0u;
+        len[c] = 0;
+    }
+}
+
+// ------------------------------------------------------------------ ICount
+// first = #{B_S <= a.end} = #{B_S < a.end + 1}; last = #{B_E < a.start};
+// count = first - last (Sec. 2.1).  a.end == 2^32-1 means first = |B|.
+
+template <int QPL>
+__device__ __forceinline__ void icount_plain(const SearchArgs& sa, const uint32_t* lds,
+                                             const uint32_t (&as)[QPL], const uint32_t (&ae)[QPL],
+                                             uint32_t (&cnt)[QPL]) {
+    constexpr int NC = 2 * QPL;
+    uint32_t x[NC], base[NC], len[NC];
+#pragma unroll
+    for (int q = 0; q < QPL; ++q) {
+        x[2 * q] = ae[q] + 1u;
+        x[2 * q + 1] = as[q];
+    }
+    const uint32_t d = sa.depth;
+    if (d) {
+        const uint32_t m = 1u << d;
+        uint32_t k[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) k[c] = 1u;
+        for (uint32_t l = 0; l < d; ++l) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) k[c] = 2u * k[c] + (lds[(c & 1) * m + k[c]] < x[c] ? 1u : 0u);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const uint64_t qb = k[c] - m;
+            base[c] = (uint32_t)((qb * sa.n) >> d);
+            len[c] = (uint32_t)(((qb + 1) * sa.n) >> d) - base[c];
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            base[c] = 0u;
+            len[c] = sa.n;
+        }
+    }
+    bisect_multi<NC>(sa.bs, sa.be, base, len, x);
+#pragma unroll
+    for (int q = 0; q < QPL; ++q) {
+        const uint32_t first = (ae[q] == 0xFFFFFFFFu) ? sa.n : base[2 * q];
+        cnt[q] = first - base[2 * q + 1];
+    }
+}
+
+template <int QPL>
+__device__ __forceinline__ void icount_learned(const SearchArgs& sa, const uint32_t (&as)[QPL],
+                                               const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL]) {
+    constexpr int NC = 2 * QPL;
+    uint32_t x[NC], base[NC], len[NC], wl[NC], wr[NC], rlo[NC], rhi[NC];
+    bool win[NC];
+#pragma unroll
+    for (int q = 0; q < QPL; ++q) {
+        x[2 * q] = ae[q] + 1u;
+        x[2 * q + 1] = as[q];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const bits_rmi_model* M = sa.rmi + (c & 1);
+        const uint32_t leaf = rmi_route(M->root_a, M->root_b, x[c]);
+        const bits_rmi_leaf* L = M->leaf + leaf;
+        const uint4 h0 = *reinterpret_cast<const uint4*>(L);                       // kmin kmax rlo cnt
+        const uint4 h1 = *reinterpret_cast<const uint4*>(&L->kinv);                // kinv err_lo err_hi loss
+        rlo[c] = h0.z;
+        rhi[c] = h0.z + h0.w;
+        win[c] = false;
+        base[c] = rlo[c];
+        len[c] = 0;
+        if (x[c] > h0.y) {
+            base[c] = rhi[c];
+        } else if (x[c] > h0.x) {
+            const int32_t off = rmi_pred_offset(L->p, h0.w, __uint_as_float(h1.x), x[c] - h0.x);
+            const int32_t pred = (int32_t)h0.z + off;
+            const int32_t lo = pred - (int32_t)h1.y, hi = pred + (int32_t)h1.z;
+            wl[c] = (uint32_t)max(lo, (int32_t)rlo[c]);
+            wr[c] = (uint32_t)min(hi, (int32_t)rhi[c]);
+            if (wr[c] < wl[c]) wr[c] = wl[c];
+            base[c] = wl[c];
+            len[c] = wr[c] - wl[c];
+            win[c] = true;
+        }
+    }
+    bisect_multi<NC>(sa.bs, sa.be, base, len, x);
+    bool any_fb = false;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (!win[c]) continue;
+        const uint32_t* K = (c & 1) ? sa.be : sa.bs;
+        const uint32_t r = base[c];
+        bool ok = true;
+        if (r == wl[c] && wl[c] != rlo[c]) ok = K[wl[c] - 1] < x[c];
+        if (r == wr[c] && wr[c] != rhi[c]) ok = ok && (K[wr[c]] >= x[c]);
+        if (!ok) {
+            base[c] = rlo[c];
+            len[c] = rhi[c] - rlo[c];
+            any_fb = true;
+            atomicAdd(sa.fallbacks, 1ull);
+        }
+    }
+    if (any_fb) bisect_multi<NC>(sa.bs, sa.be, base, len, x);
+#pragma unroll
+    for (int q = 0; q < QPL; ++q) {
+        const uint32_t first = (ae[q] == 0xFFFFFFFFu) ? sa.n : base[2 * q];
+        cnt[q] = first - base[2 * q + 1];
+    }
+}
+
+template <int QPL, bool LEARNED>
+__device__ __forceinline__ void icount(const SearchArgs& sa, const uint32_t* lds, const uint32_t (&as)[QPL],
+                                       const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL]) {
+    if constexpr (LEARNED)
+        icount_learned<QPL>(sa, as, ae, cnt);
+    else
+        icount_plain<QPL>(sa, lds, as, ae, cnt);
+}
+
+// ------------------------------------------------------------------ counting kernel
+// Persistent grid over tiles of blockDim*QPL queries; query i of a tile is
+// loaded by lane (i mod blockDim), so every load of a query round is
+// coalesced.  Totals: uint64 wave sum, one atomic per wave.
+
+template <int QPL, bool LEARNED>
+__global__ void __launch_bounds__(1024) k_count(SearchArgs sa, const uint32_t* __restrict__ a_start,
+                                                const uint32_t* __restrict__ a_end, uint64_t na,
+                                                uint32_t* __restrict__ counts, unsigned long long* total) {
+    extern __shared__ uint32_t lds[];
+    if (!LEARNED) {
+        stage_tree(lds, sa.tree, sa.tree_stride, sa.depth);
+        __syncthreads();
+    }
+    const uint64_t tile = (uint64_t)blockDim.x * QPL;
+    const uint64_t ntiles = (na + tile - 1) / tile;
+    uint64_t acc = 0;
+    uint32_t bad = 0;
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        uint32_t as[QPL], ae[QPL], cnt[QPL];
+        bool valid[QPL];
+#pragma unroll
+        for (int q = 0; q < QPL; ++q) {
+            const uint64_t i = t * tile + (uint64_t)q * blockDim.x + threadIdx.x;
+            valid[q] = i < na;
+            as[q] = valid[q] ? a_start[i] : 0u;
+            ae[q] = valid[q] ? a_end[i] : 0u;
+            if (as[q] > ae[q]) {
+                bad = 1;
+                valid[q] = false;
+                ae[q] = as[q];
+            }
+        }
+        icount<QPL, LEARNED>(sa, lds, as, ae, cnt);
+#pragma unroll
+        for (int q = 0; q < QPL; ++q) {
+            const uint64_t i = t * tile + (uint64_t)q * blockDim.x + threadIdx.x;
+            const uint32_t c = valid[q] ? cnt[q] : 0u;
+            if (counts && i < na) counts[i] = c;
+            acc += c;
+        }
+    }
+    if (bad) atomicOr(sa.status, BITS_FLAG_INTERVAL);
+    if (total) {
+        acc = wave_sum_u64(acc);
+        if ((threadIdx.x & (kWave - 1)) == 0 && acc) atomicAdd(total, (unsigned long long)acc);
+    }
+}
+
+// ------------------------------------------------------------------ Monte-Carlo
+// Work item = (shuffle s, tile of blockDim*QPL queries); items are walked by a
+// persistent grid.  Query i of shuffle s starts at off_i + floor(u * span_i /
+// 2^64), u = the first two Philox words of counter g = (s0 + s) * na + i.
+// OBSERVED counts the unshuffled queries instead (same exclusion of queries
+// with span 0, i.e. outside their chromosome).
+
+template <int QPL, bool LEARNED, bool OBSERVED>
+__global__ void __launch_bounds__(1024)
+    k_mc(SearchArgs sa, const uint32_t* __restrict__ a_start, const uint32_t* __restrict__ a_end,
+         const uint32_t* __restrict__ off, const uint32_t* __restrict__ span, const uint32_t* __restrict__ len,
+         uint64_t na, uint64_t seed, uint64_t s0, uint64_t nshuf, uint64_t tiles_per_shuf,
+         unsigned long long* __restrict__ totals) {
+    extern __shared__ uint32_t lds[];
+    if (!LEARNED) {
+        stage_tree(lds, sa.tree, sa.tree_stride, sa.depth);
+        __syncthreads();
+    }
+    const uint64_t tile = (uint64_t)blockDim.x * QPL;
+    const uint64_t nitems = nshuf * tiles_per_shuf;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint64_t s = it / tiles_per_shuf;
+        const uint64_t t = it - s * tiles_per_shuf;
+        uint32_t as[QPL], ae[QPL], cnt[QPL];
+        bool valid[QPL];
+#pragma unroll
+        for (int q = 0; q < QPL; ++q) {
+            const uint64_t i = t * tile + (uint64_t)q * blockDim.x + threadIdx.x;
+            const uint32_t sp = i < na ? span[i] : 0u;
+            valid[q] = sp != 0u;
+            if (OBSERVED) {
+                as[q] = valid[q] ? a_start[i] : 0u;
+                ae[q] = valid[q] ? a_end[i] : 0u;
+            } else {
+                const uint64_t g = (s0 + s) * na + i;
+                uint32_t c0 = (uint32_t)g, c1 = (uint32_t)(g >> 32), c2 = 0u, c3 = 0u;
+                philox4x32_10(c0, c1, c2, c3, k0, k1);
+                const uint64_t u = ((uint64_t)c1 << 32) | c0;
+                const uint32_t local = (uint32_t)__umul64hi(u, (uint64_t)sp);
+                as[q] = valid[q] ? off[i] + local : 0u;
+                ae[q] = valid[q] ? as[q] + len[i] - 1u : 0u;
+            }
+        }
+        icount<QPL, LEARNED>(sa, lds, as, ae, cnt);
+        uint64_t acc = 0;
+#pragma unroll
+        for (int q = 0; q < QPL; ++q) acc += valid[q] ? cnt[q] : 0u;
+        acc = wave_sum_u64(acc);
+        if ((threadIdx.x & (kWave - 1)) == 0 && acc) atomicAdd(totals + s, (unsigned long long)acc);
+    }
+}
+
+struct ChromTab {
+    uint32_t n;
+    uint32_t off[BITS_MAX_CHROM + 1];   // off[c] = sum of lengths before c; off[n] = genome size
+};
+
+// Per-query (chromosome offset, number of legal starts, length), computed
+// once and reused by every shuffle.  span = 0 marks a query outside its
+// chromosome (or start > end).
+__global__ void k_mc_prepare(const uint32_t* __restrict__ a_start, const uint32_t* __restrict__ a_end, uint64_t na,
+                             ChromTab ct, uint32_t* __restrict__ off, uint32_t* __restrict__ span,
+                             uint32_t* __restrict__ len, uint32_t* status) {
+    uint32_t bad = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t s = a_start[i], e = a_end[i];
+        uint32_t lo = 0, hi = ct.n;          // chromosome = last c with off[c] <= s
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (ct.off[mid] <= s) lo = mid; else hi = mid;
+        }
+        const uint32_t c = lo;
+        const bool ok = s <= e && s >= ct.off[c] && (uint64_t)e < (uint64_t)ct.off[c + 1];
+        const uint32_t L = e - s + 1u;
+        off[i] = ct.off[c];
+        len[i] = ok ? L : 1u;
+        span[i] = ok ? (ct.off[c + 1] - ct.off[c]) - L + 1u : 0u;
+        if (!ok) bad |= (s > e) ? BITS_FLAG_INTERVAL : BITS_FLAG_CHROM;
+    }
+    if (bad) atomicOr(status, bad);
+}
+
+__global__ void k_mc_tail(const unsigned long long* __restrict__ totals, uint64_t nshuf,
+                          const unsigned long long* observed, unsigned long long* n_ge,
+                          unsigned long long* n_le) {
+    __shared__ unsigned long long red[2][16];
+    const unsigned long long obs = *observed;
+    uint64_t ge = 0, le = 0;
+    for (uint64_t s = threadIdx.x; s < nshuf; s += blockDim.x) {
+        ge += totals[s] >= obs;
+        le += totals[s] <= obs;
+    }
+    ge = wave_sum_u64(ge);
+    le = wave_sum_u64(le);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        red[0][w] = ge;
+        red[1][w] = le;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long g = 0, l = 0;
+        for (int k = 0; k < (int)(blockDim.x / kWave); ++k) {
+            g += red[0][k];
+            l += red[1][k];
+        }
+        *n_ge = g;
+        *n_le = l;
+    }
+}
+
+// ------------------------------------------------------------------ projection
+__global__ void k_project(ChromTab ct, const uint32_t* __restrict__ chrom, const uint32_t* __restrict__ ls,
+                          const uint32_t* __restrict__ le, uint64_t n, uint32_t* __restrict__ gs,
+                          uint32_t* __restrict__ ge, uint32_t* status) {
+    uint32_t bad = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = chrom[i], s = ls[i], e = le[i];
+        const bool cok = c < ct.n;
+        const uint32_t o = cok ? ct.off[c] : 0u;
+        const uint32_t clen = cok ? ct.off[c + 1] - ct.off[c] : 0u;
+        if (!cok || e >= clen) bad |= BITS_FLAG_CHROM;
+        if (s > e) bad |= BITS_FLAG_INTERVAL;
+        gs[i] = o + s;
+        ge[i] = o + e;
+    }
+    if (bad && status) atomicOr(status, bad);
+}
+
+// ------------------------------------------------------------------ batched pairs
+// Each workgroup owns the contiguous item range [wg_begin[w], wg_begin[w+1]);
+// items are sorted by reference, so the LDS tree is re-staged only when the
+// reference changes.  Consecutive logical workgroups run on the same XCD
+// (hardware dispatches workgroups round-robin over the 8 XCDs), so an XCD's
+// L2 sees few distinct references.
+template <int QPL>
+__global__ void __launch_bounds__(1024)
+    k_batch(const BatchRef* __restrict__ refs, const BatchQuery* __restrict__ qs, const BatchItem* __restrict__ items,
+            const uint32_t* __restrict__ wg_begin, uint32_t n_wg, uint32_t n_ref, uint32_t max_depth,
+            unsigned long long* __restrict__ pair_totals, uint32_t* status) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t g = gridDim.x, b = blockIdx.x;
+    const uint32_t per_xcd = g / 8u;
+    const uint32_t w = (g % 8u == 0u) ? (b % 8u) * per_xcd + b / 8u : b;
+    if (w >= n_wg) return;
+    const uint32_t i0 = wg_begin[w], i1 = wg_begin[w + 1];
+    uint32_t cur = 0xFFFFFFFFu;
+    SearchArgs sa{};
+    uint32_t bad = 0;
+    for (uint32_t it = i0; it < i1; ++it) {
+        const BatchItem item = items[it];
+        if (item.r != cur) {
+            __syncthreads();
+            const BatchRef R = refs[item.r];
+            sa.bs = R.bs;
+            sa.be = R.be;
+            sa.tree = R.tree;
+            sa.n = R.n;
+            sa.tree_stride = R.tree_stride;
+            sa.depth = min(R.depth, max_depth);
+            stage_tree(lds, sa.tree, sa.tree_stride, sa.depth);
+            cur = item.r;
+            __syncthreads();
+        }
+        const BatchQuery Q = qs[item.q];
+        uint32_t as[QPL], ae[QPL], cnt[QPL];
+        bool valid[QPL];
+#pragma unroll
+        for (int q = 0; q < QPL; ++q) {
+            const uint32_t k = (uint32_t)q * blockDim.x + threadIdx.x;
+            const uint64_t i = (uint64_t)item.begin + k;
+            valid[q] = k < item.count;
+            as[q] = valid[q] ? Q.as[i] : 0u;
+            ae[q] = valid[q] ? Q.ae[i] : 0u;
+            if (as[q] > ae[q]) {
+                bad = 1;
+                valid[q] = false;
+                ae[q] = as[q];
+            }
+        }
+        if (sa.n) {
+            icount_plain<QPL>(sa, lds, as, ae, cnt);
+        } else {
+#pragma unroll
+            for (int q = 0; q < QPL; ++q) cnt[q] = 0;
+        }
+        uint64_t acc = 0;
+#pragma unroll
+        for (int q = 0; q < QPL; ++q) acc += valid[q] ? cnt[q] : 0u;
+        acc = wave_sum_u64(acc);
+        if ((threadIdx.x & (kWave - 1)) == 0 && acc)
+            atomicAdd(pair_totals + (uint64_t)item.q * n_ref + item.r, (unsigned long long)acc);
+    }
+    if (bad) atomicOr(status, BITS_FLAG_INTERVAL);
+}
+
+// ------------------------------------------------------------------ fills
+__global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------------------ host side
+
+int device_cu_count() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+        cached[dev] = cu;
+    }
+    return cached[dev];
+}
+
+// Workgroups resident per CU for a kernel/block/LDS combination (cached).
+static int blocks_per_cu(const void* kernel, int block, size_t lds) {
+    static std::mutex mu;
+    static std::unordered_map<uint64_t, int> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const uint64_t key = ((uint64_t)(uintptr_t)kernel * 1315423911u) ^ ((uint64_t)block << 40) ^ ((uint64_t)lds << 8) ^ (uint64_t)dev;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, lds) != hipSuccess || nb <= 0) nb = 1;
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = nb;
+    return nb;
+}
+
+static uint32_t persistent_grid(const void* kernel, const LaunchCfg& cfg, size_t lds, uint64_t work_items) {
+    uint64_t g = cfg.grid ? cfg.grid : (uint64_t)device_cu_count() * blocks_per_cu(kernel, cfg.block, lds);
+    if (g > work_items) g = work_items;
+    if (g < 1) g = 1;
+    return (uint32_t)g;
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s) {
+    if (!n) return hipSuccess;
+    uint64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_fill_u64, dim3((uint32_t)g), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
+    if (!n) return hipSuccess;
+    uint64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)g), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+template <int QPL, bool LEARNED>
+static hipError_t launch_count_t(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
+                                 uint64_t na, uint32_t* counts, unsigned long long* total, hipStream_t s) {
+    const size_t lds = LEARNED ? 0 : tree_lds_words(sa.depth) * sizeof(uint32_t);
+    const uint64_t tile = (uint64_t)cfg.block * QPL;
+    const void* kern = (const void*)k_count<QPL, LEARNED>;
+    const uint32_t grid = persistent_grid(kern, cfg, lds, (na + tile - 1) / tile);
+    hipLaunchKernelGGL((k_count<QPL, LEARNED>), dim3(grid), dim3(cfg.block), lds, s, sa, as, ae, na, counts, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
+                        uint64_t na, uint32_t* counts, unsigned long long* total, hipStream_t s) {
+    if (!na) return hipSuccess;
+    const bool L = cfg.path == BITS_PATH_LEARNED;
+    switch (cfg.qpl) {
+        case 1: return L ? launch_count_t<1, true>(sa, cfg, as, ae, na, counts, total, s)
+                         : launch_count_t<1, false>(sa, cfg, as, ae, na, counts, total, s);
+        case 4: return L ? launch_count_t<4, true>(sa, cfg, as, ae, na, counts, total, s)
+                         : launch_count_t<4, false>(sa, cfg, as, ae, na, counts, total, s);
+        default: return L ? launch_count_t<2, true>(sa, cfg, as, ae, na, counts, total, s)
+                          : launch_count_t<2, false>(sa, cfg, as, ae, na, counts, total, s);
+    }
+}
+
+static int fill_chrom_tab(const uint32_t* chrom_len, uint32_t n_chrom, ChromTab* ct) {
+    if (n_chrom == 0 || n_chrom > BITS_MAX_CHROM) return BITS_E_ARG;
+    uint64_t acc = 0;
+    ct->n = n_chrom;
+    for (uint32_t c = 0; c < n_chrom; ++c) {
+        ct->off[c] = (uint32_t)acc;
+        acc += chrom_len[c];
+        if (acc > 0xFFFFFFFFull) return BITS_E_CHROM;
+    }
+    ct->off[n_chrom] = (uint32_t)acc;
+    for (uint32_t c = n_chrom + 1; c <= BITS_MAX_CHROM; ++c) ct->off[c] = (uint32_t)acc;
+    return BITS_OK;
+}
+
+hipError_t launch_mc_prepare(const uint32_t* as, const uint32_t* ae, uint64_t na, const uint32_t* chrom_len,
+                             uint32_t n_chrom, uint32_t* off, uint32_t* span, uint32_t* len, uint32_t* status,
+                             hipStream_t s) {
+    ChromTab ct;
+    if (fill_chrom_tab(chrom_len, n_chrom, &ct) != BITS_OK) return hipErrorInvalidValue;
+    if (!na) return hipSuccess;
+    uint64_t g = (na + 255) / 256;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_mc_prepare, dim3((uint32_t)g), dim3(256), 0, s, as, ae, na, ct, off, span, len, status);
+    return hipGetLastError();
+}
+
+template <int QPL, bool LEARNED>
+static hipError_t launch_mc_t(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
+                              const uint32_t* off, const uint32_t* span, const uint32_t* len, uint64_t na,
+                              uint64_t seed, uint64_t s0, uint64_t nshuf, unsigned long long* totals,
+                              unsigned long long* observed, hipStream_t s) {
+    const size_t lds = LEARNED ? 0 : tree_lds_words(sa.depth) * sizeof(uint32_t);
+    const uint64_t tile = (uint64_t)cfg.block * QPL;
+    const uint64_t tps = (na + tile - 1) / tile;
+    if (observed) {
+        const void* ko = (const void*)k_mc<QPL, LEARNED, true>;
+        const uint32_t go = persistent_grid(ko, cfg, lds, tps);
+        hipLaunchKernelGGL((k_mc<QPL, LEARNED, true>), dim3(go), dim3(cfg.block), lds, s, sa, as, ae, off, span,
+                           len, na, seed, s0, (uint64_t)1, tps, observed);
+    }
+    if (nshuf) {
+        const void* km = (const void*)k_mc<QPL, LEARNED, false>;
+        const uint32_t gm = persistent_grid(km, cfg, lds, nshuf * tps);
+        hipLaunchKernelGGL((k_mc<QPL, LEARNED, false>), dim3(gm), dim3(cfg.block), lds, s, sa, as, ae, off, span,
+                           len, na, seed, s0, nshuf, tps, totals);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mc(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
+                     const uint32_t* off, const uint32_t* span, const uint32_t* len, uint64_t na, uint64_t seed,
+                     uint64_t s0, uint64_t nshuf, unsigned long long* totals, unsigned long long* observed,
+                     hipStream_t s) {
+    if (!na) return hipSuccess;
+    const bool L = cfg.path == BITS_PATH_LEARNED;
+    switch (cfg.qpl) {
+        case 1: return L ? launch_mc_t<1, true>(sa, cfg, as, ae, off, span, len, na, seed, s0, nshuf, totals, observed, s)
+                         : launch_mc_t<1, false>(sa, cfg, as, ae, off, span, len, na, seed, s0, nshuf, totals, observed, s);
+        case 4: return L ? launch_mc_t<4, true>(sa, cfg, as, ae, off, span, len, na, seed, s0, nshuf, totals, observed, s)
+                         : launch_mc_t<4, false>(sa, cfg, as, ae, off, span, len, na, seed, s0, nshuf, totals, observed, s);
+        default: return L ? launch_mc_t<2, true>(sa, cfg, as, ae, off, span, len, na, seed, s0, nshuf, totals, observed, s)
+                          : launch_mc_t<2, false>(sa, cfg, as, ae, off, span, len, na, seed, s0, nshuf, totals, observed, s);
+    }
+}
+
+hipError_t launch_mc_tail(const unsigned long long* totals, uint64_t nshuf, const unsigned long long* observed,
+                          unsigned long long* n_ge, unsigned long long* n_le, hipStream_t s) {
+    hipLaunchKernelGGL(k_mc_tail, dim3(1), dim3(1024), 0, s, totals, nshuf, observed, n_ge, n_le);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const uint32_t* chrom_len, uint32_t n_chrom, const uint32_t* chrom, const uint32_t* ls,
+                          const uint32_t* le, uint64_t n, uint32_t* gs, uint32_t* ge, uint32_t* status,
+                          hipStream_t s) {
+    ChromTab ct;
+    if (fill_chrom_tab(chrom_len, n_chrom, &ct) != BITS_OK) return hipErrorInvalidValue;
+    if (!n) return hipSuccess;
+    uint64_t g = (n + 255) / 256;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_project, dim3((uint32_t)g), dim3(256), 0, s, ct, chrom, ls, le, n, gs, ge, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchRef* refs, const BatchQuery* qs, const BatchItem* items, const uint32_t* wg_begin,
+                        uint32_t n_wg, uint32_t n_ref, uint32_t max_depth, const LaunchCfg& cfg,
+                        unsigned long long* pair_totals, uint32_t* status, hipStream_t s) {
+    const size_t lds = tree_lds_words(max_depth) * sizeof(uint32_t);
+    switch (cfg.qpl) {
+        case 1:
+            hipLaunchKernelGGL(k_batch<1>, dim3(n_wg), dim3(cfg.block), lds, s, refs, qs, items, wg_begin, n_wg, n_ref,
+                               max_depth, pair_totals, status);
+            break;
+        case 4:
+            hipLaunchKernelGGL(k_batch<4>, dim3(n_wg), dim3(cfg.block), lds, s, refs, qs, items, wg_begin, n_wg, n_ref,
+                               max_depth, pair_totals, status);
+            break;
+        default:
+            hipLaunchKernelGGL(k_batch<2>, dim3(n_wg), dim3(cfg.block), lds, s, refs, qs, items, wg_begin, n_wg, n_ref,
+                               max_depth, pair_totals, status);
+            break;
+    }
+    return hipGetLastError();
+}
+
+int batch_blocks_per_cu(uint32_t qpl, uint32_t block, uint32_t max_depth) {
+    const size_t lds = tree_lds_words(max_depth) * sizeof(uint32_t);
+    const void* k = qpl == 1 ? (const void*)k_batch<1> : qpl == 4 ? (const void*)k_batch<4> : (const void*)k_batch<2>;
+    return blocks_per_cu(k, (int)block, lds);
+}
+
+}  // namespace bits

@@ -1,0 +1,421 @@
+// On-device LSD radix sort of uint32 keys (the two Sort steps of Algorithm 2)
+// and the Eytzinger top-tree build.
+//
+// Segmented and keys-only: every segment (e.g. B_S and B_E of one or many
+// references) is sorted independently in the same launches.  Four passes of
+// 8-bit digits, reduce-then-scan per pass:
+//   tile histogram -> per (segment, digit) scan over tiles -> stable scatter.
+// A digit that is constant over every segment is skipped (decided on the
+// device, so the sort never waits for the host).  Inputs are never written.
+#include <string.h>
+
+#include <vector>
+
+#include "bits_internal.hpp"
+
+namespace bits {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / kWave;
+constexpr uint32_t kPerWave = 1024;            // keys per wave per tile
+constexpr uint32_t kTile = kPerWave * kWaves;  // 4096 keys per tile
+constexpr int kRounds = kPerWave / kWave;      // 16 rounds of 64 keys
+
+struct SegDesc {
+    const uint32_t* in;
+    uint32_t* ping;
+    uint32_t* out;
+    uint32_t n;
+    uint32_t tile0;   // first global tile of the segment
+};
+static_assert(sizeof(SegDesc) == 32, "SegDesc layout");
+
+struct SortPlan {
+    uint32_t active[4];
+    uint32_t src[4];   // 0 = input, 1 = ping, 2 = output
+    uint32_t dst[4];
+    uint32_t n_active;
+    uint32_t pad[3];
+};
+
+constexpr int kDescChunk = 96;
+struct DescChunk {
+    SegDesc d[kDescChunk];
+};
+
+__device__ __forceinline__ uint32_t seg_of_tile(const SegDesc* descs, uint32_t nseg, uint32_t t) {
+    uint32_t lo = 0, hi = nseg;      // last s with tile0 <= t
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (descs[mid].tile0 <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ const uint32_t* buf_ro(const SegDesc& d, uint32_t sel) {
+    return sel == 0 ? d.in : sel == 1 ? d.ping : d.out;
+}
+__device__ __forceinline__ uint32_t* buf_rw(const SegDesc& d, uint32_t sel) {
+    return sel == 1 ? d.ping : d.out;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) tmp[w] = x;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+        if (k < w) pre += tmp[k];
+        tot += tmp[k];
+    }
+    __syncthreads();
+    if (total) *total = tot;
+    return pre + x - v;
+}
+
+__global__ void k_write_descs(SegDesc* dst, DescChunk chunk, uint32_t count) {
+    const uint32_t i = threadIdx.x;
+    if (i < count) dst[i] = chunk.d[i];
+}
+
+// All four digit histograms of every segment in one read of the input.
+// Workgroup b walks a contiguous range of tiles, accumulating in LDS and
+// flushing when the segment changes.
+__global__ void __launch_bounds__(kThreads) k_hist_all(const SegDesc* __restrict__ descs, uint32_t nseg,
+                                                       uint32_t ntiles, uint32_t* __restrict__ seg_hist) {
+    __shared__ uint32_t h[4][256];
+    const uint32_t t0 = (uint32_t)((uint64_t)ntiles * blockIdx.x / gridDim.x);
+    const uint32_t t1 = (uint32_t)((uint64_t)ntiles * (blockIdx.x + 1) / gridDim.x);
+    for (int k = threadIdx.x; k < 1024; k += kThreads) (&h[0][0])[k] = 0;
+    __syncthreads();
+    uint32_t cur = 0xFFFFFFFFu;
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint32_t s = seg_of_tile(descs, nseg, t);
+        if (s != cur) {
+            if (cur != 0xFFFFFFFFu) {
+                __syncthreads();
+                for (int k = threadIdx.x; k < 1024; k += kThreads) {
+                    const uint32_t v = (&h[0][0])[k];
+                    if (v) atomicAdd(seg_hist + (size_t)cur * 1024 + k, v);
+                    (&h[0][0])[k] = 0;
+                }
+                __syncthreads();
+            }
+            cur = s;
+        }
+        const SegDesc d = descs[s];
+        const uint32_t begin = (t - d.tile0) * kTile;
+        const uint32_t cnt = min(kTile, d.n - begin);
+        const uint32_t* src = d.in + begin;
+        for (uint32_t k = threadIdx.x; k < cnt; k += kThreads) {
+            const uint32_t key = src[k];
+            atomicAdd(&h[0][key & 255u], 1u);
+            atomicAdd(&h[1][(key >> 8) & 255u], 1u);
+            atomicAdd(&h[2][(key >> 16) & 255u], 1u);
+            atomicAdd(&h[3][key >> 24], 1u);
+        }
+    }
+    __syncthreads();
+    if (cur != 0xFFFFFFFFu) {
+        for (int k = threadIdx.x; k < 1024; k += kThreads) {
+            const uint32_t v = (&h[0][0])[k];
+            if (v) atomicAdd(seg_hist + (size_t)cur * 1024 + k, v);
+        }
+    }
+}
+
+// Block (s, p): exclusive prefix over digits of segment s's pass-p histogram;
+// marks pass p active when the digit takes two or more values in s.
+__global__ void __launch_bounds__(kThreads) k_seg_scan(const uint32_t* __restrict__ seg_hist,
+                                                       uint32_t* __restrict__ seg_pre, SortPlan* plan) {
+    __shared__ uint32_t tmp[kWaves];
+    const uint32_t sp = blockIdx.x;   // s * 4 + p
+    const uint32_t v = seg_hist[(size_t)sp * 256 + threadIdx.x];
+    uint32_t tot = 0;
+    seg_pre[(size_t)sp * 256 + threadIdx.x] = block_excl_scan(v, tmp, &tot);
+    const uint64_t nz = __ballot(v != 0);
+    __shared__ uint32_t nzc[kWaves];
+    if ((threadIdx.x & (kWave - 1)) == 0) nzc[threadIdx.x / kWave] = (uint32_t)__popcll(nz);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t c = 0;
+        for (int k = 0; k < kWaves; ++k) c += nzc[k];
+        if (c >= 2) atomicOr(&plan->active[sp & 3u], 1u);
+    }
+}
+
+// Buffer schedule: the last active pass writes the output, earlier ones
+// alternate so that the first reads the input.
+__global__ void k_plan(SortPlan* plan) {
+    if (threadIdx.x != 0) return;
+    uint32_t na = 0;
+    for (int p = 0; p < 4; ++p) na += plan->active[p] ? 1u : 0u;
+    plan->n_active = na;
+    uint32_t r = 0, prev_dst = 0;
+    for (int p = 0; p < 4; ++p) {
+        if (!plan->active[p]) continue;
+        const uint32_t dst = ((na - 1 - r) % 2 == 0) ? 2u : 1u;
+        plan->src[p] = r == 0 ? 0u : prev_dst;
+        plan->dst[p] = dst;
+        prev_dst = dst;
+        ++r;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_tile_hist(const SegDesc* __restrict__ descs, uint32_t nseg,
+                                                        const SortPlan* __restrict__ plan, int p,
+                                                        uint32_t ntiles, uint32_t* __restrict__ H) {
+    if (!plan->active[p]) return;
+    __shared__ uint32_t h[256];
+    const uint32_t t = blockIdx.x;
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t s = seg_of_tile(descs, nseg, t);
+    const SegDesc d = descs[s];
+    const uint32_t begin = (t - d.tile0) * kTile;
+    const uint32_t cnt = min(kTile, d.n - begin);
+    const uint32_t* src = buf_ro(d, plan->src[p]) + begin;
+    const uint32_t shift = 8u * p;
+    for (uint32_t k = threadIdx.x; k < cnt; k += kThreads) atomicAdd(&h[(src[k] >> shift) & 255u], 1u);
+    __syncthreads();
+    H[(size_t)threadIdx.x * ntiles + t] = h[threadIdx.x];
+}
+
+// Block (s, digit): exclusive scan of H[digit][tiles of s] in place.
+__global__ void __launch_bounds__(kThreads) k_tile_scan(const SegDesc* __restrict__ descs,
+                                                        const SortPlan* __restrict__ plan, int p,
+                                                        uint32_t ntiles, uint32_t* __restrict__ H) {
+    if (!plan->active[p]) return;
+    __shared__ uint32_t tmp[kWaves];
+    const uint32_t s = blockIdx.x >> 8, dg = blockIdx.x & 255u;
+    const SegDesc d = descs[s];
+    const uint32_t nt = (d.n + kTile - 1) / kTile;
+    uint32_t* row = H + (size_t)dg * ntiles + d.tile0;
+    const uint32_t per = (nt + kThreads - 1) / kThreads;
+    const uint32_t b = threadIdx.x * per, e = min(nt, b + per);
+    uint32_t sum = 0;
+    for (uint32_t k = b; k < e; ++k) sum += row[k];
+    uint32_t run = block_excl_scan(sum, tmp, nullptr);
+    for (uint32_t k = b; k < e; ++k) {
+        const uint32_t v = row[k];
+        row[k] = run;
+        run += v;
+    }
+}
+
+// Stable scatter of one tile.  Wave w ranks keys [w*1024, (w+1)*1024) of the
+// tile in 16 rounds; within a round, lanes holding the same digit are found
+// with 8 ballots and ranked by lane order.  The tile is then sorted by digit
+// in LDS and written out in digit runs (coalesced).
+__global__ void __launch_bounds__(kThreads) k_scatter(const SegDesc* __restrict__ descs, uint32_t nseg,
+                                                      const SortPlan* __restrict__ plan, int p, uint32_t ntiles,
+                                                      const uint32_t* __restrict__ H,
+                                                      const uint32_t* __restrict__ seg_pre) {
+    if (!plan->active[p]) return;
+    __shared__ uint32_t keys_lds[kTile];
+    __shared__ uint32_t wcnt[kWaves][256];
+    __shared__ uint32_t dstart[256];
+    __shared__ uint32_t goff[256];
+    __shared__ uint32_t tmp[kWaves];
+    const uint32_t t = blockIdx.x;
+    const uint32_t s = seg_of_tile(descs, nseg, t);
+    const SegDesc d = descs[s];
+    const uint32_t begin = (t - d.tile0) * kTile;
+    const uint32_t cnt = min(kTile, d.n - begin);
+    const uint32_t* src = buf_ro(d, plan->src[p]) + begin;
+    uint32_t* dst = buf_rw(d, plan->dst[p]);
+    const uint32_t shift = 8u * p;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    for (int k = threadIdx.x; k < kWaves * 256; k += kThreads) (&wcnt[0][0])[k] = 0;
+    __syncthreads();
+
+    uint32_t key[kRounds], rank[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const uint32_t idx = (uint32_t)w * kPerWave + (uint32_t)r * kWave + lane;
+        key[r] = idx < cnt ? src[idx] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const uint32_t idx = (uint32_t)w * kPerWave + (uint32_t)r * kWave + lane;
+        const bool valid = idx < cnt;
+        const uint32_t dg = (key[r] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (dg >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t before = (uint32_t)__popcll(peers & lt_mask);
+        uint32_t old = 0;
+        if (valid) old = wcnt[w][dg];
+        rank[r] = old + before;
+        if (valid && before == 0) wcnt[w][dg] = old + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    {
+        const uint32_t dg = threadIdx.x;
+        uint32_t tot = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) {
+            const uint32_t c = wcnt[k][dg];
+            wcnt[k][dg] = tot;
+            tot += c;
+        }
+        dstart[dg] = block_excl_scan(tot, tmp, nullptr);
+        goff[dg] = seg_pre[((size_t)s * 4 + p) * 256 + dg] + H[(size_t)dg * ntiles + t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const uint32_t idx = (uint32_t)w * kPerWave + (uint32_t)r * kWave + lane;
+        if (idx < cnt) {
+            const uint32_t dg = (key[r] >> shift) & 255u;
+            keys_lds[dstart[dg] + wcnt[w][dg] + rank[r]] = key[r];
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < cnt; k += kThreads) {
+        const uint32_t v = keys_lds[k];
+        const uint32_t dg = (v >> shift) & 255u;
+        dst[goff[dg] + (k - dstart[dg])] = v;
+    }
+}
+
+// When no digit varies the input is already sorted (all keys equal): copy.
+__global__ void k_copy_if_idle(const SegDesc* __restrict__ descs, uint32_t nseg, const SortPlan* __restrict__ plan) {
+    if (plan->n_active) return;
+    const uint32_t t = blockIdx.x;
+    const uint32_t s = seg_of_tile(descs, nseg, t);
+    const SegDesc d = descs[s];
+    const uint32_t begin = (t - d.tile0) * kTile;
+    const uint32_t cnt = min(kTile, d.n - begin);
+    for (uint32_t k = threadIdx.x; k < cnt; k += kThreads) d.out[begin + k] = d.in[begin + k];
+}
+
+// Eytzinger top tree: node k (level l = floor(log2 k), j = k - 2^l) holds
+// keys[p - 1] with p = floor((2j + 1) n / 2^(l + 1)), i.e. the last key of
+// the bucket left of boundary p.  The first 2^d - 1 nodes form the depth-d
+// tree for every d <= depth.
+__global__ void k_build_tree(const uint32_t* __restrict__ keys, uint64_t n, uint32_t depth, uint32_t* __restrict__ tree) {
+    const uint32_t m = 1u << depth;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < m; k += gridDim.x * blockDim.x) {
+        if (k == 0) {
+            tree[0] = 0u;
+            continue;
+        }
+        const uint32_t l = 31u - __clz(k);
+        const uint64_t j = k - (1u << l);
+        const uint64_t pos = ((2 * j + 1) * n) >> (l + 1);
+        tree[k] = keys[pos - 1];
+    }
+}
+
+struct WsLayout {
+    size_t descs, plan, seg_hist, seg_pre, H, ping, total;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static WsLayout ws_layout(const uint64_t* n, uint32_t nseg) {
+    uint64_t ntiles = 0, nkeys = 0;
+    for (uint32_t s = 0; s < nseg; ++s) {
+        ntiles += (n[s] + kTile - 1) / kTile;
+        nkeys += n[s];
+    }
+    WsLayout L;
+    size_t o = 0;
+    L.descs = o; o = align256(o + sizeof(SegDesc) * nseg);
+    L.plan = o; o = align256(o + sizeof(SortPlan));
+    L.seg_hist = o; o = align256(o + (size_t)nseg * 1024 * 4);
+    L.seg_pre = o; o = align256(o + (size_t)nseg * 1024 * 4);
+    L.H = o; o = align256(o + (size_t)ntiles * 256 * 4);
+    L.ping = o; o = align256(o + (size_t)nkeys * 4);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+size_t sort_workspace_bytes(const uint64_t* n, uint32_t nseg) { return ws_layout(n, nseg).total; }
+
+int launch_sort(const SortSeg* segs, uint32_t nseg, void* ws, size_t ws_bytes, hipStream_t s) {
+    std::vector<uint64_t> ns(nseg);
+    for (uint32_t i = 0; i < nseg; ++i) {
+        if (segs[i].n > 0xFFFFFFFFull) return BITS_E_ARG;
+        ns[i] = segs[i].n;
+    }
+    const WsLayout L = ws_layout(ns.data(), nseg);
+    if (ws_bytes < L.total) return BITS_E_WORKSPACE;
+    char* base = (char*)ws;
+    SegDesc* descs = (SegDesc*)(base + L.descs);
+    SortPlan* plan = (SortPlan*)(base + L.plan);
+    uint32_t* seg_hist = (uint32_t*)(base + L.seg_hist);
+    uint32_t* seg_pre = (uint32_t*)(base + L.seg_pre);
+    uint32_t* H = (uint32_t*)(base + L.H);
+    uint32_t* ping = (uint32_t*)(base + L.ping);
+
+    // Descriptors, written by small kernels from by-value chunks so the call
+    // stays asynchronous and capturable.
+    uint32_t tile0 = 0;
+    uint64_t koff = 0;
+    for (uint32_t c0 = 0; c0 < nseg; c0 += kDescChunk) {
+        DescChunk ch;
+        memset(&ch, 0, sizeof(ch));
+        const uint32_t cnt = (nseg - c0) < (uint32_t)kDescChunk ? (nseg - c0) : (uint32_t)kDescChunk;
+        for (uint32_t i = 0; i < cnt; ++i) {
+            const SortSeg& g = segs[c0 + i];
+            ch.d[i].in = g.in;
+            ch.d[i].out = g.out;
+            ch.d[i].ping = ping + koff;
+            ch.d[i].n = (uint32_t)g.n;
+            ch.d[i].tile0 = tile0;
+            tile0 += (uint32_t)((g.n + kTile - 1) / kTile);
+            koff += g.n;
+        }
+        hipLaunchKernelGGL(k_write_descs, dim3(1), dim3(128), 0, s, descs + c0, ch, cnt);
+    }
+    const uint32_t ntiles = tile0;
+    BITS_CHECK_HIP(launch_fill_u32((uint32_t*)plan, sizeof(SortPlan) / 4, 0u, s));
+    BITS_CHECK_HIP(launch_fill_u32(seg_hist, (uint64_t)nseg * 1024, 0u, s));
+    if (ntiles == 0) {
+        BITS_CHECK_HIP(hipGetLastError());
+        return BITS_OK;
+    }
+
+    const uint32_t hg = ntiles < 2048u ? ntiles : 2048u;
+    hipLaunchKernelGGL(k_hist_all, dim3(hg), dim3(kThreads), 0, s, descs, nseg, ntiles, seg_hist);
+    hipLaunchKernelGGL(k_seg_scan, dim3(nseg * 4), dim3(kThreads), 0, s, seg_hist, seg_pre, plan);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, s, plan);
+    for (int p = 0; p < 4; ++p) {
+        hipLaunchKernelGGL(k_tile_hist, dim3(ntiles), dim3(kThreads), 0, s, descs, nseg, plan, p, ntiles, H);
+        hipLaunchKernelGGL(k_tile_scan, dim3(nseg * 256), dim3(kThreads), 0, s, descs, plan, p, ntiles, H);
+        hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(kThreads), 0, s, descs, nseg, plan, p, ntiles, H, seg_pre);
+    }
+    hipLaunchKernelGGL(k_copy_if_idle, dim3(ntiles), dim3(kThreads), 0, s, descs, nseg, plan);
+    BITS_CHECK_HIP(hipGetLastError());
+    return BITS_OK;
+}
+
+hipError_t launch_build_tree(const uint32_t* keys, uint64_t n, uint32_t depth, uint32_t* tree, hipStream_t s) {
+    const uint32_t m = 1u << depth;
+    const uint32_t g = (m + 255) / 256;
+    hipLaunchKernelGGL(k_build_tree, dim3(g), dim3(256), 0, s, keys, n, depth, tree);
+    return hipGetLastError();
+}
+
+}  // namespace bits

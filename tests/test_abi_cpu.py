@@ -1,0 +1,78 @@
+"""CPU checks of the C ABI: libbits.so loads, exports every entry point that
+include/bits.h declares, and rejects bad host-side arguments before touching
+a device.  No compute call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bits.h")
+LIB = os.path.join(ROOT, "paper_1208_3407_amd", "libbits.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bits_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libbits.so is not built: run __graft_entry__.build()")
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_host_only_entry_points(lib):
+    assert lib.bits_version() >= 1
+    lib.bits_strerror.restype = ctypes.c_char_p
+    assert lib.bits_strerror(4) == b"workspace too small"
+    lib.bits_pvalue.restype = ctypes.c_double
+    lib.bits_pvalue.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    assert lib.bits_pvalue(0, 9999) == 1.0 / 10000.0
+    assert lib.bits_pvalue(3, 99) == 4.0 / 100.0
+    sz = ctypes.c_size_t(0)
+    assert lib.bits_ref_bytes(ctypes.c_uint64(1000), 13, 1, ctypes.byref(sz)) == 0 and sz.value > 8000
+    assert lib.bits_ref_bytes(ctypes.c_uint64(2**33), 13, 0, ctypes.byref(sz)) == 1
+    assert lib.bits_sort_ref_workspace(ctypes.c_uint64(10**6), ctypes.byref(sz)) == 0 and sz.value > 8 * 10**6
+    assert lib.bits_mc_workspace(ctypes.c_uint64(100), ctypes.byref(sz)) == 0 and sz.value >= 1200
+
+
+def test_ref_init_carves_block_on_host(lib):
+    class Ref(ctypes.Structure):
+        _fields_ = [("n", ctypes.c_uint64), ("depth", ctypes.c_uint32), ("learned", ctypes.c_uint32),
+                    ("bs", ctypes.c_void_p), ("be", ctypes.c_void_p), ("tree", ctypes.c_void_p),
+                    ("rmi", ctypes.c_void_p), ("status", ctypes.c_void_p), ("block", ctypes.c_void_p),
+                    ("block_bytes", ctypes.c_size_t)]
+    sz = ctypes.c_size_t(0)
+    assert lib.bits_ref_bytes(ctypes.c_uint64(100), 13, 0, ctypes.byref(sz)) == 0
+    r = Ref()
+    base = 1 << 20    # a fake, 256-aligned address: ref_init only computes offsets
+    assert lib.bits_ref_init(ctypes.c_void_p(base), sz, ctypes.c_uint64(100), 13, 0, ctypes.byref(r)) == 0
+    assert r.depth == 6                      # floor(log2 100)
+    assert r.status == base and r.tree > base and r.be > r.bs > r.tree
+    assert r.be + 400 <= base + sz.value
+    assert lib.bits_ref_init(ctypes.c_void_p(base), ctypes.c_size_t(sz.value - 1), ctypes.c_uint64(100), 13, 0,
+                             ctypes.byref(r)) == 4
+    assert lib.bits_ref_init(ctypes.c_void_p(base + 4), sz, ctypes.c_uint64(100), 13, 0, ctypes.byref(r)) == 1
+
+
+def test_bad_arguments_rejected_before_any_device_work(lib):
+    # null reference / null query pointers with n > 0 -> BITS_E_ARG (1)
+    assert lib.bits_count(None, None, None, ctypes.c_uint64(5), None, None, None) == 1
+    assert lib.bits_count_per_query(None, None, None, ctypes.c_uint64(5), None, None, None, None) == 1
+    lens = (ctypes.c_uint32 * 2)(10, 20)
+    assert lib.bits_project(lens, 0, None, None, None, ctypes.c_uint64(0), None, None, None, None) == 1
+    big = (ctypes.c_uint32 * 2)(0xF0000000, 0xF0000000)
+    assert lib.bits_project(big, 2, None, None, None, ctypes.c_uint64(0), None, None, None, None) == 3
+    assert lib.bits_rmi_leaf_grad(None, None, 5000, None, None, None, None) == 1
+    assert lib.bits_batch_create(None, 0, None, None, None, 0, None, None, ctypes.c_size_t(0), None, None, None) == 1

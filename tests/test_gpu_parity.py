@@ -1,0 +1,277 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+element by element, on seeded synthetic inputs.  Counts, ranks, per-shuffle
+totals and tail counts are integers and must be bit-exact."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1208_3407_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+from paper_1208_3407_amd import bits  # noqa: E402  (loads libbits.so; raises if not built)
+
+DEV = torch.device("cuda", 0)
+
+
+def up(x):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.uint32))).to(DEV)
+
+
+def down(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def project_both(lengths, S):
+    gs, ge = bits.bits_project(lengths, up(S.chrom), up(S.start), up(S.end))
+    os_, oe = oracle.project(lengths, S.chrom, S.start, S.end)
+    assert np.array_equal(down(gs), os_) and np.array_equal(down(ge), oe)
+    return gs, ge, os_, oe
+
+
+LAUNCHES = [
+    {"path": bits.BITS_PATH_PLAIN},
+    {"path": bits.BITS_PATH_PLAIN, "block": 256, "qpl": 1, "depth": 0},
+    {"path": bits.BITS_PATH_PLAIN, "block": 512, "qpl": 4, "depth": 9},
+    {"path": bits.BITS_PATH_PLAIN, "block": 1024, "qpl": 2, "depth": 13, "grid": 7},
+]
+
+
+def test_w0_full_against_oracle_and_bruteforce():
+    note("case: W0 10k x 10k")
+    lengths, A, B = datagen.w0_sets()
+    a_s, a_e, oa_s, oa_e = project_both(lengths, A)
+    b_s, b_e, ob_s, ob_e = project_both(lengths, B)
+    ref = bits.bits_sort_ref(b_s, b_e)
+    assert np.array_equal(down(ref.sorted_starts()), oracle.sort_u32(ob_s))
+    assert np.array_equal(down(ref.sorted_ends()), oracle.sort_u32(ob_e))
+    exp, tot = oracle.counter(oa_s, oa_e, ob_s, ob_e)
+    for lp in LAUNCHES:
+        c, t = bits.bits_count_per_query(ref, a_s, a_e, launch=lp)
+        assert np.array_equal(down(c), exp), lp
+        assert int(down(t)[0]) == tot
+        assert int(down(bits.bits_count(ref, a_s, a_e, launch=lp))[0]) == tot
+    bc, bt = oracle.count_bruteforce(oa_s[:500], oa_e[:500], ob_s[:500], ob_e[:500])
+    r5 = bits.bits_sort_ref(b_s[:500].contiguous(), b_e[:500].contiguous())
+    c5, t5 = bits.bits_count_per_query(r5, a_s[:500].contiguous(), a_e[:500].contiguous())
+    assert np.array_equal(down(c5), bc) and int(down(t5)[0]) == bt
+    assert bits.bits_get_status(ref) == 0
+
+
+@pytest.mark.parametrize("na,nb", [(1, 1), (3, 70_001), (65_537, 4_099), (300_000, 500_000)])
+def test_genome_scale_shapes_plain_and_learned(na, nb):
+    note("case: W1 shape %d x %d" % (na, nb))
+    lengths, A, B = datagen.w1_sets(seed=3, n_a=na, n_b=nb)
+    a_s, a_e, oa_s, oa_e = project_both(lengths, A)
+    b_s, b_e, ob_s, ob_e = project_both(lengths, B)
+    exp, tot = oracle.counter(oa_s, oa_e, ob_s, ob_e, threads=8)
+    ref = bits.bits_sort_ref(b_s, b_e, learned=True, train={"epochs": 60})
+    assert np.array_equal(down(ref.sorted_starts()), np.sort(ob_s))
+    assert np.array_equal(down(ref.sorted_ends()), np.sort(ob_e))
+    for lp in LAUNCHES + [{"path": bits.BITS_PATH_LEARNED, "qpl": q} for q in (1, 2, 4)]:
+        c, t = bits.bits_count_per_query(ref, a_s, a_e, launch=lp)
+        assert np.array_equal(down(c), exp), lp
+        assert int(down(t)[0]) == tot, lp
+    assert bits.bits_get_status(ref) == 0
+
+
+def test_edge_cases():
+    note("case: edge cases")
+    z = torch.empty(0, dtype=torch.uint32, device=DEV)
+    # empty reference
+    ref0 = bits.bits_sort_ref(z, z)
+    c, t = bits.bits_count_per_query(ref0, up([1, 5]), up([3, 9]))
+    assert list(down(c)) == [0, 0] and int(down(t)[0]) == 0
+    # empty queries
+    ref1 = bits.bits_sort_ref(up([1, 2]), up([5, 6]))
+    c, t = bits.bits_count_per_query(ref1, z, z)
+    assert c.numel() == 0 and int(down(t)[0]) == 0
+    # all keys equal (every digit constant: sort copies), duplicates
+    ref2 = bits.bits_sort_ref(up([7] * 5000), up([7] * 5000), learned=True, train={"epochs": 5})
+    for lp in ({"path": 1}, {"path": 2}):
+        c, _ = bits.bits_count_per_query(ref2, up([0, 7, 8, 0]), up([6, 7, 9, 100]), launch=lp)
+        assert list(down(c)) == [0, 5000, 0, 5000]
+    # extreme coordinates: end = 2^32 - 1 and start = 0
+    M = 0xFFFFFFFF
+    bs, be = [0, 5, M - 1, M], [0, M, M, M]
+    qs, qe = [0, M, 3, M - 1], [M, M, 4, M - 1]
+    ref3 = bits.bits_sort_ref(up(bs), up(be), learned=True, train={"epochs": 5})
+    exp, _ = oracle.count_bruteforce(qs, qe, bs, be)
+    for lp in ({"path": 1}, {"path": 2}):
+        c, _ = bits.bits_count_per_query(ref3, up(qs), up(qe), launch=lp)
+        assert np.array_equal(down(c), exp), lp
+    # golden fixtures (contained intervals, touching endpoints)
+    import os
+    gdir = os.path.join(os.path.dirname(__file__), "golden")
+    for name in ("contained.txt", "touching.txt"):
+        A, B, E = [], [], []
+        for line in open(os.path.join(gdir, name)):
+            f = line.split("#")[0].split()
+            if not f:
+                continue
+            (B if f[0] == "B" else A).append((int(f[1]), int(f[2])))
+            if f[0] == "A":
+                E.append(int(f[3]))
+        A, B = np.array(A, np.uint32), np.array(B, np.uint32)
+        r = bits.bits_sort_ref(up(B[:, 0]), up(B[:, 1]))
+        c, _ = bits.bits_count_per_query(r, up(A[:, 0]), up(A[:, 1]))
+        assert list(down(c)) == E, name
+    # inverted query interval: flagged, counted as zero
+    c, _ = bits.bits_count_per_query(ref1, up([4, 1]), up([3, 2]))
+    assert list(down(c)) == [0, 2]
+    assert bits.bits_get_status(ref1) & bits.BITS_FLAG_INTERVAL
+
+
+def test_heavy_duplicates_and_clustered_keys():
+    note("case: duplicates")
+    r = np.random.default_rng(9)
+    nb = 200_000
+    s = r.integers(0, 3000, size=nb).astype(np.uint32) * np.uint32(1000)
+    e = s + r.integers(0, 4, size=nb).astype(np.uint32) * np.uint32(500)
+    qs = r.integers(0, 3_000_000, size=50_000).astype(np.uint32)
+    qe = qs + r.integers(0, 2000, size=50_000).astype(np.uint32)
+    exp, tot = oracle.counter(qs, qe, s, e, threads=8)
+    ref = bits.bits_sort_ref(up(s), up(e), learned=True, train={"epochs": 40})
+    for lp in ({"path": 1}, {"path": 2}, {"path": 1, "depth": 4, "qpl": 4}):
+        c, t = bits.bits_count_per_query(ref, up(qs), up(qe), launch=lp)
+        assert np.array_equal(down(c), exp), lp
+        assert int(down(t)[0]) == tot
+
+
+def test_segmented_sort_many_references():
+    note("case: segmented sort")
+    r = np.random.default_rng(5)
+    sizes = [0, 1, 4095, 4096, 4097, 100_000, 12_345]
+    sets = []
+    for n in sizes:
+        a = r.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
+        b = r.integers(0, 2**20, size=n, dtype=np.uint64).astype(np.uint32)
+        sets.append((a, b))
+    refs = bits.bits_sort_refs([(up(a), up(b)) for a, b in sets])
+    for (a, b), ref in zip(sets, refs):
+        assert np.array_equal(down(ref.sorted_starts()), oracle.sort_u32(a))
+        assert np.array_equal(down(ref.sorted_ends()), oracle.sort_u32(b))
+
+
+def test_monte_carlo_per_shuffle_totals():
+    note("case: MC small")
+    lengths, A, B = datagen.w2_sets(seed=1, n_a=3000, n_b=60_000)
+    a_s, a_e, oa_s, oa_e = project_both(lengths, A)
+    b_s, b_e, ob_s, ob_e = project_both(lengths, B)
+    prep = oracle.mc_prepare(lengths, oa_s, oa_e)
+    sbs, sbe = np.sort(ob_s), np.sort(ob_e)
+    exp = oracle.mc_totals(sbs, sbe, prep, 7, 0, 40, threads=8)
+    obs = oracle.counter(oa_s, oa_e, ob_s, ob_e)[1]
+    ge, le = oracle.mc_tail(exp, obs)
+    ref = bits.bits_sort_ref(b_s, b_e, learned=True, train={"epochs": 40})
+    for lp in ({"path": 1}, {"path": 2}, {"path": 1, "qpl": 1, "block": 256}, {"path": 2, "qpl": 4}):
+        mc = bits.bits_mc_pvalue(ref, a_s, a_e, lengths, seed=7, s0=0, s1=40, launch=lp)
+        assert np.array_equal(down(mc.totals), exp), lp
+        assert int(down(mc.observed)[0]) == obs
+        assert int(down(mc.n_ge)[0]) == ge and int(down(mc.n_le)[0]) == le
+    # a shuffle range continues the same stream
+    part = bits.bits_mc_pvalue(ref, a_s, a_e, lengths, seed=7, s0=17, s1=40)
+    assert np.array_equal(down(part.totals), exp[17:])
+    assert bits.bits_pvalue(ge, 40) == (1.0 + ge) / 41.0
+    assert bits.bits_get_status(ref) == 0
+
+
+def test_monte_carlo_rejects_query_outside_chromosome():
+    note("case: MC chrom flag")
+    lengths = np.array([100, 200], np.uint32)
+    b_s, b_e = np.array([0, 150, 100], np.uint32), np.array([10, 160, 299], np.uint32)
+    ref = bits.bits_sort_ref(up(b_s), up(b_e))
+    # query 0 crosses the end of chromosome 0; query 1 is valid
+    mc = bits.bits_mc_pvalue(ref, up([95, 120]), up([105, 130]), lengths, seed=7, s0=0, s1=6)
+    t = down(mc.totals)
+    assert bits.bits_get_status(ref) & bits.BITS_FLAG_CHROM
+    off1, span1, len1 = oracle.mc_prepare(lengths, np.array([120], np.uint32), np.array([130], np.uint32))
+    off = np.array([0, off1[0]], np.uint32)
+    span = np.array([1, span1[0]], np.uint32)
+    for s in range(6):
+        st = oracle.mc_placements(7, s, off, span)[1:2]     # counter g = 2 s + 1
+        _, exp = oracle.counter(st, st + len1 - np.uint32(1), b_s, b_e)
+        assert int(t[s]) == exp, s
+    assert int(down(mc.observed)[0]) == oracle.counter(np.array([120], np.uint32), np.array([130], np.uint32),
+                                                       b_s, b_e)[1]
+
+
+def test_batch_pairs_graph_replay():
+    note("case: batch")
+    lengths, Q, R = datagen.w3_sets(seed=2, n_q=5, n_r=7, q_range=(10, 30_000), r_range=(100, 80_000))
+    qd, qo = [], []
+    for S in Q:
+        s, e, os_, oe = project_both(lengths, S)
+        qd.append((s, e))
+        qo.append((os_, oe))
+    rd, ro = [], []
+    for S in R:
+        s, e, os_, oe = project_both(lengths, S)
+        rd.append((s, e))
+        ro.append((os_, oe))
+    refs = bits.bits_sort_refs(rd)
+    exp = np.zeros((len(Q), len(R)), np.uint64)
+    for i, (qs, qe) in enumerate(qo):
+        for j, (rs, re_) in enumerate(ro):
+            exp[i, j] = oracle.counter(qs, qe, rs, re_)[1]
+    for lp in (None, {"block": 256, "qpl": 1, "depth": 5}, {"block": 1024, "qpl": 4}):
+        plan = bits.bits_batch_create(refs, qd, launch=lp)
+        for rep in range(3):
+            tot = bits.bits_batch_run(plan)
+            got = down(tot).reshape(len(Q), len(R))
+            assert np.array_equal(got, exp), (lp, rep)
+            # eager work between replays
+            bits.bits_count(refs[0], qd[0][0], qd[0][1])
+            torch.cuda.synchronize()
+        bits.bits_batch_destroy(plan)
+
+
+def test_learned_gradient_matches_oracle():
+    note("case: leaf gradient")
+    r = np.random.default_rng(12)
+    for m in (1, 100, 4096):
+        p = r.normal(0, 1, 49).astype(np.float32)
+        u = r.uniform(0, 1, m).astype(np.float32)
+        t = np.sort(r.uniform(0, 1, m)).astype(np.float32)
+        g, loss = bits.bits_rmi_leaf_grad(torch.from_numpy(u).to(DEV), torch.from_numpy(t).to(DEV),
+                                          torch.from_numpy(p).to(DEV))
+        lo, go = oracle.rmi_loss_grad(p, u, t)
+        g = down(g).astype(np.float64)
+        assert np.max(np.abs(g - go)) <= 1e-3 * np.max(np.abs(go)) + 1e-6, (m, g, go)
+        assert abs(float(down(loss)[0]) - lo) <= 1e-4 * max(1.0, lo)
+
+
+def test_learned_index_metadata():
+    note("case: learned metadata")
+    lengths, _, B = datagen.w1_sets(seed=4, n_a=1, n_b=400_000)
+    b_s, b_e, ob_s, ob_e = project_both(lengths, B)
+    ref = bits.bits_sort_ref(b_s, b_e, learned=True, train={"epochs": 100})
+    raw = down(ref.rmi_bytes())
+    for a, keys in enumerate((np.sort(ob_s), np.sort(ob_e))):
+        base = a * bits.RMI_MODEL_BYTES
+        hdr = raw[base:base + 256]
+        fit_a, fit_b = np.frombuffer(hdr[8:24].tobytes(), np.float64)
+        oa, ob = oracle.linear_fit(keys)
+        assert abs(fit_a - oa) <= 1e-9 * abs(oa) and abs(fit_b - ob) <= 1e-6 * max(1.0, abs(ob))
+        leaves = raw[base + 256: base + bits.RMI_MODEL_BYTES].reshape(4096, 256)
+        u32 = leaves[:, :16].copy().view(np.uint32)
+        rlo, cnt = u32[:, 2].astype(np.int64), u32[:, 3].astype(np.int64)
+        # leaves tile the rank range in order
+        assert rlo[0] == 0 and rlo[-1] + cnt[-1] == len(keys)
+        assert np.all(rlo[1:] == rlo[:-1] + cnt[:-1])
+        nz = cnt > 0
+        assert np.array_equal(u32[nz, 0], keys[rlo[nz]])
+        assert np.array_equal(u32[nz, 1], keys[rlo[nz] + cnt[nz] - 1])
+    info = bits.bits_rmi_info(ref)
+    assert info["mean_window"] >= 1 and info["max_window"] >= 1
