@@ -1,0 +1,295 @@
+"""Benchmark of the BITS hot path on one MI355X.
+
+Workload (learned index at scale): B = 50,000,000 intervals (half uniform,
+half around 20,000 Gaussian clusters, log-normal lengths median 200 bp) and
+A = 50,000,000 uniform intervals on a 24-chromosome synthetic genome, plus a
+Monte-Carlo run of 1,000 shuffles of the first 1,000,000 intervals of A.
+
+One step is one pass of the whole hot path on inputs already resident in
+HBM (chromosome-local coordinates):
+  projection of A and B -> on-device radix sort of B_S and B_E, Eytzinger top
+  trees, learned CDF index trained on the device -> per-query counts of all
+  of A through the learned index -> 1,000 Monte-Carlo shuffles (one
+  persistent launch) with observed total and tail counts.
+value = A-intervals counted per second over the step (50M queries + 1,000 x
+1M shuffled queries per step).  Printed as one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+N_B = 50_000_000
+N_A = 50_000_000
+N_MC = 1_000_000
+N_SHUF = 1_000
+MC_SEED = 7
+# Bytes per A-interval evaluation moved by the search (byte model of the
+# design notes): 12 B compulsory + two searches of ~1.25 128-byte lines each
+# through the learned index; two searches of ~3 lines each on the plain path.
+BYTES_PER_EVAL_LEARNED = 330.0
+BYTES_PER_EVAL_PLAIN = 780.0
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_mc_learned_w4.json")
+# launch shapes the autotuner picked on MI355X for this workload (used with --no-autotune)
+RECORDED_LEARNED = {"block": 1024, "qpl": 1, "depth": 0, "grid": 0, "path": 2}
+RECORDED_PLAIN = {"block": 256, "qpl": 1, "depth": 13, "grid": 0, "path": 1}
+KERNEL_SOURCES = ["paper_1208_3407_amd/csrc/search.hip", "paper_1208_3407_amd/csrc/bits_internal.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(evals_per_launch):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, if it was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return float(t["bytes_per_eval"]) * evals_per_launch
+
+
+def autotune(bits, ref, a_s, a_e, path, cache_key):
+    cache_path = os.path.join(os.path.expanduser("~"), ".cache", "paper_1208_3407_amd", "autotune.json")
+    try:
+        with open(cache_path) as f:
+            cache = json.load(f)
+    except (OSError, ValueError):
+        cache = {}
+    if cache_key in cache:
+        return cache[cache_key]
+    best, ms = bits.bits_autotune_count(ref, a_s, a_e, path)
+    d = best.as_dict()
+    cache[cache_key] = d
+    try:
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+    except OSError:
+        pass
+    log("autotune path %d: %s (%.2f ms)" % (path, d, ms))
+    return d
+
+
+def cpu_baseline(lengths, A, B, threads):
+    """The CPU oracle on a bounded sample of the same workload."""
+    import oracle
+
+    t0 = time.perf_counter()
+    a_s, a_e = oracle.project(lengths, A.chrom[:8 * N_MC], A.start[:8 * N_MC], A.end[:8 * N_MC])
+    b_s, b_e = oracle.project(lengths, B.chrom, B.start, B.end)
+    sbs, sbe = oracle.sort_u32(b_s), oracle.sort_u32(b_e)
+    t_setup = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    _, _ = oracle.count_sorted(sbs, sbe, a_s, a_e, threads=threads)
+    t_count = time.perf_counter() - t1
+    prep = oracle.mc_prepare(lengths, a_s[:N_MC], a_e[:N_MC])
+    t2 = time.perf_counter()
+    n_shuf = threads
+    oracle.mc_totals(sbs, sbe, prep, MC_SEED, 0, n_shuf, threads=threads)
+    t_mc = time.perf_counter() - t2
+    n_evals = len(a_s) + n_shuf * N_MC
+    return {
+        "value": n_evals / (t_count + t_mc),
+        "unit": "A-intervals/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "oracle (C, -O2) on the same workload: projection + qsort of the full 5e7-interval B "
+                  "(%.1f s, not in value), per-query counts of the first %d A-intervals on %d threads "
+                  "(%.2f s) and %d Monte-Carlo shuffles of the 1e6 MC queries on %d threads (%.2f s); "
+                  "value = %d evaluations / counting time" % (t_setup, len(a_s), threads, t_count, n_shuf, threads,
+                                                              t_mc, n_evals),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the recorded best launch shapes instead of timing candidates")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="finish with a plain 1 GiB device copy (HBM byte-counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1208_3407_amd import bits, datagen
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+
+    t0 = time.time()
+    lengths, A, B = datagen.w4_sets(seed=1, n_a=N_A, n_b=N_B)
+    log("data %.1f s" % (time.time() - t0))
+
+    def up(x):
+        return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+    dA = [up(A.chrom), up(A.start), up(A.end)]
+    dB = [up(B.chrom), up(B.start), up(B.end)]
+    ref = bits.bits_ref_init(N_B, 13, learned=True)
+    ws = bits._scratch(bits.bits_sort_ref_workspace(N_B), dev)
+    mc_ws = bits._scratch(bits.bits_mc_workspace(N_MC), dev)
+    counts = torch.empty(N_A, dtype=torch.uint32, device=dev)
+    total = torch.empty(1, dtype=torch.uint64, device=dev)
+    mc_out = bits.MCResult(torch.empty(N_SHUF, dtype=torch.uint64, device=dev),
+                           torch.empty(1, dtype=torch.uint64, device=dev),
+                           torch.empty(1, dtype=torch.uint64, device=dev),
+                           torch.empty(1, dtype=torch.uint64, device=dev))
+    train = {"epochs": args.epochs}
+
+    # launch shapes from the autotuner (outside the timed region)
+    a_s, a_e = bits.bits_project(lengths, *dA)
+    b_s, b_e = bits.bits_project(lengths, *dB)
+    bits.bits_sort_ref(b_s, b_e, learned=True, train=train, ref=ref, workspace=ws)
+    tag = "%s|nA=%d|nB=%d" % (torch.cuda.get_device_properties(0).gcnArchName, N_A, N_B)
+    if args.no_autotune:
+        lp_learned, lp_plain = dict(RECORDED_LEARNED), dict(RECORDED_PLAIN)
+    else:
+        lp_learned = autotune(bits, ref, a_s, a_e, bits.BITS_PATH_LEARNED, "learned|" + tag)
+        lp_plain = autotune(bits, ref, a_s, a_e, bits.BITS_PATH_PLAIN, "plain|" + tag)
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    mc_ms = []
+
+    def step(record):
+        a_s, a_e = bits.bits_project(lengths, *dA)
+        b_s, b_e = bits.bits_project(lengths, *dB)
+        if record:
+            ev[0].record()
+        bits.bits_sort_ref(b_s, b_e, learned=True, train=train, ref=ref, workspace=ws)
+        if record:
+            ev[1].record()
+        bits.bits_count_per_query(ref, a_s, a_e, launch=lp_learned, counts=counts, total=total)
+        if record:
+            ev[2].record()
+        bits.bits_mc_pvalue(ref, a_s[:N_MC], a_e[:N_MC], lengths, MC_SEED, 0, N_SHUF, launch=lp_learned,
+                            workspace=mc_ws, out=mc_out)
+        if record:
+            ev[3].record()
+        return a_s, a_e
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    phase = {"setup_ms": [], "count_ms": [], "mc_ms": []}
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+        ev[3].synchronize()
+        phase["setup_ms"].append(ev[0].elapsed_time(ev[1]))
+        phase["count_ms"].append(ev[1].elapsed_time(ev[2]))
+        phase["mc_ms"].append(ev[2].elapsed_time(ev[3]))
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ms_per_step = t_total * 1e3 / args.steps
+    evals = N_A + N_SHUF * N_MC
+    value = evals / (ms_per_step / 1e3)
+    status = bits.bits_get_status(ref)
+    learned_total = int(total.cpu().numpy()[0])
+    mc_totals = mc_out.totals.cpu().numpy()
+
+    # plain binary-search path on the same reference, outside the timed region
+    a_s, a_e = bits.bits_project(lengths, *dA)
+    def timed(fn, reps=3):
+        best = 1e30
+        for _ in range(reps):
+            ev[4].record()
+            fn()
+            ev[5].record()
+            ev[5].synchronize()
+            best = min(best, ev[4].elapsed_time(ev[5]))
+        return best
+    t_plain = timed(lambda: bits.bits_count_per_query(ref, a_s, a_e, launch=lp_plain, counts=counts, total=total))
+    plain_total = int(total.cpu().numpy()[0])
+    t_learned = timed(lambda: bits.bits_count_per_query(ref, a_s, a_e, launch=lp_learned, counts=counts,
+                                                        total=total))
+    mc_plain = bits.MCResult(torch.empty(N_SHUF, dtype=torch.uint64, device=dev),
+                             torch.empty(1, dtype=torch.uint64, device=dev),
+                             torch.empty(1, dtype=torch.uint64, device=dev),
+                             torch.empty(1, dtype=torch.uint64, device=dev))
+    t_mc_plain = timed(lambda: bits.bits_mc_pvalue(ref, a_s[:N_MC], a_e[:N_MC], lengths, MC_SEED, 0, N_SHUF,
+                                                   launch=lp_plain, workspace=mc_ws, out=mc_plain), reps=1)
+    agree = (plain_total == learned_total) and np.array_equal(mc_plain.totals.cpu().numpy(), mc_totals)
+    info = bits.bits_rmi_info(ref)
+
+    mc_avg = float(np.mean(phase["mc_ms"]))
+    mc_evals = N_SHUF * N_MC + N_MC
+    achieved = BYTES_PER_EVAL_LEARNED * mc_evals / (mc_avg / 1e3) / 1e9
+    traffic = load_traffic(N_SHUF * N_MC)
+    result = {
+        "metric": "A-intervals counted/s (learned vs binary-search index); MC shuffles/s",
+        "value": value,
+        "unit": "A-intervals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "learned index at scale: B=5e7 clustered, A=5e7 uniform, MC 1000 x 1e6 "
+                               "(24-chromosome genome)",
+                   "n_b": N_B, "n_a": N_A, "mc_queries": N_MC, "mc_shuffles": N_SHUF, "train_epochs": args.epochs,
+                   "launch_learned": lp_learned, "launch_plain": lp_plain},
+        "phases_ms": {k: float(np.mean(v)) for k, v in phase.items()},
+        "count_learned_aps": N_A / (t_learned / 1e3),
+        "count_plain_aps": N_A / (t_plain / 1e3),
+        "learned_speedup": t_plain / t_learned,
+        "mc_shuffles_per_s": N_SHUF / (mc_avg / 1e3),
+        "mc_shuffles_per_s_plain": N_SHUF / (t_mc_plain / 1e3),
+        "learned_equals_plain": bool(agree),
+        "rmi": info,
+        "status": status,
+        "roofline": {"bound": "hbm", "kernel": "k_mc<learned> (Monte-Carlo shuffles)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_eval_model": BYTES_PER_EVAL_LEARNED,
+                     "launch_ms": mc_avg},
+    }
+    if not args.no_cpu_baseline:
+        threads = max(1, min(16, os.cpu_count() or 1))
+        result["cpu_baseline"] = cpu_baseline(lengths, A, B, threads)
+    print(json.dumps(result), flush=True)
+    if args.copy_calibration:
+        x = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+
+
+if __name__ == "__main__":
+    main()
