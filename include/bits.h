@@ -56,6 +56,7 @@ typedef enum bits_status {
 #define BITS_RMI_LEAVES  4096u    /* leaf models per learned index */
 #define BITS_RMI_HIDDEN  16u      /* hidden ReLU units per leaf model */
 #define BITS_RMI_PARAMS  49u      /* w1[16], b1[16], w2[16], b2 */
+#define BITS_RMI_MAX_POINTS 2048u /* training points per leaf */
 
 /* Search path selection for a call (bits_launch.path). */
 #define BITS_PATH_AUTO    0u      /* learned index if the reference has one, else plain */
@@ -118,7 +119,7 @@ typedef struct bits_rmi_model {
 /* Training settings for the learned index (NULL = defaults). */
 typedef struct bits_train {
     uint32_t epochs;      /* full-batch Adam steps per leaf (default 300; 0 = init only) */
-    uint32_t max_points;  /* training points per leaf, stride-sampled (default 4096, <= 4096) */
+    uint32_t max_points;  /* training points per leaf, stride-sampled (default and max 2048) */
     float lr;             /* Adam step size (default 2e-3) */
     float beta1, beta2;   /* Adam moments (defaults 0.9, 0.999) */
 } bits_train;
@@ -303,7 +304,7 @@ int bits_autotune_count(const bits_ref *ref, const uint32_t *d_a_start, const ui
 /* Loss and gradient of one leaf model over m points, computed by the same
  * device code the training kernel runs (fp32):
  *   loss = mean_i (y(u_i) - t_i)^2,  y(u) = b2 + sum_j w2_j relu(w1_j u + b1_j)
- *   d_u, d_t      device float[m], m <= 4096
+ *   d_u, d_t      device float[m], m <= BITS_RMI_MAX_POINTS (2048)
  *   d_params      device float[49]  (w1[16], b1[16], w2[16], b2)
  *   d_grad        device float[49];  d_loss device float[1] */
 int bits_rmi_leaf_grad(const float *d_u, const float *d_t, uint32_t m, const float *d_params,

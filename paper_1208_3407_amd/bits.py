@@ -247,7 +247,7 @@ def bits_ref_init(n: int, depth: int = BITS_MAX_DEPTH, learned: bool = False, bl
 def _train(train: Optional[dict]):
     if train is None:
         return None
-    t = bits_train(int(train.get("epochs", 300)), int(train.get("max_points", 4096)), float(train.get("lr", 2e-3)),
+    t = bits_train(int(train.get("epochs", 300)), int(train.get("max_points", 2048)), float(train.get("lr", 2e-3)),
                    float(train.get("beta1", 0.9)), float(train.get("beta2", 0.999)))
     return ctypes.byref(t)
 

@@ -52,10 +52,10 @@ bool ref_ok(const bits_ref* r) {
 }
 
 bits_train train_defaults(const bits_train* t) {
-    bits_train d{300u, 4096u, 2e-3f, 0.9f, 0.999f};
+    bits_train d{300u, BITS_RMI_MAX_POINTS, 2e-3f, 0.9f, 0.999f};
     if (!t) return d;
     bits_train r = *t;
-    if (r.max_points == 0 || r.max_points > 4096) r.max_points = 4096;
+    if (r.max_points == 0 || r.max_points > BITS_RMI_MAX_POINTS) r.max_points = BITS_RMI_MAX_POINTS;
     if (!(r.lr > 0.0f)) r.lr = d.lr;
     if (!(r.beta1 > 0.0f && r.beta1 < 1.0f)) r.beta1 = d.beta1;
     if (!(r.beta2 > 0.0f && r.beta2 < 1.0f)) r.beta2 = d.beta2;
@@ -583,7 +583,7 @@ int bits_autotune_count(const bits_ref* ref, const uint32_t* d_a_start, const ui
 
 int bits_rmi_leaf_grad(const float* d_u, const float* d_t, uint32_t m, const float* d_params, float* d_grad,
                        float* d_loss, void* stream) {
-    if (m > 4096 || !d_params || !d_grad || !d_loss || (m && (!d_u || !d_t))) return BITS_E_ARG;
+    if (m > BITS_RMI_MAX_POINTS || !d_params || !d_grad || !d_loss || (m && (!d_u || !d_t))) return BITS_E_ARG;
     BITS_CHECK_HIP(launch_rmi_leaf_grad(d_u, d_t, m, d_params, d_grad, d_loss, (hipStream_t)stream));
     return BITS_OK;
 }

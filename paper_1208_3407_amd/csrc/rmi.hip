@@ -5,10 +5,9 @@
 //          every leaf owns a contiguous rank range [rlo, rlo + cnt));
 //   leaf:  y(u) = b2 + sum_j w2_j relu(w1_j u + b1_j), 16 hidden units, u the
 //          key normalised to the leaf's key range, y the normalised rank.
-// Each leaf is trained on the device by full-batch Adam on up to 4096
-// stride-sampled keys (one workgroup per leaf, all state on chip, fixed-order
-// reductions, hence deterministic).  After training, the same workgroup
-// measures the largest over- and under-prediction of the rank over all of
+// Each leaf is trained on the device by full-batch Adam on up to 2048
+// stride-sampled keys (one wave per leaf, all state in registers, fixed-order
+// reductions, hence deterministic).  After training, the same wave measures the largest over- and under-prediction of the rank over all of
 // the leaf's keys with the query-time prediction code; queries search that
 // window, verify the result and fall back to bisection of the leaf's range.
 #include "bits_internal.hpp"
@@ -19,7 +18,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
-constexpr uint32_t kMaxPoints = 4096;
 constexpr int kSumBlocks = 512;
 constexpr int kNP = BITS_RMI_PARAMS;   // 49
 
@@ -120,50 +118,64 @@ __global__ void k_rmi_bounds(Pair2 P, uint64_t n) {
     }
 }
 
-// Block-wide loss gradient of the leaf model over points (u[k], t[k]),
-// k < m.  Every thread of the block returns; threads 0..49 hold the totals
-// in out[0..49] (48 gradients, b2's, then the summed squared residual).
-__device__ void block_grad(const float* u, const float* t, uint32_t m, const float* p, float (*red)[52],
-                           float* out) {
-    float g[kNP + 1];
+// ---------------------------------------------------------------- leaf training
+// One wave trains one leaf.  Its up to 2048 training points sit in the
+// wave's LDS slice; the 49 parameters are uniform across the wave; lane
+// k < 49 owns parameter k's Adam moments.  Reductions are wave-only (row
+// rotations, then two lane exchanges), so the sum order is fixed and
+// training is deterministic.
+
+template <int CTRL>
+__device__ __forceinline__ float row_ror(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 64 lanes, returned to every lane.
+__device__ __forceinline__ float wave_allsum(float v) {
+    v += row_ror<0x128>(v);   // row_ror:8
+    v += row_ror<0x124>(v);   // row_ror:4
+    v += row_ror<0x122>(v);   // row_ror:2
+    v += row_ror<0x121>(v);   // row_ror:1
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+}
+
+// Loss gradient of the leaf model over points (u[j], t[j]), j < m: lane l
+// takes points l, l + 64, ... in order.  g[0..48] are the parameter
+// gradients of mean (y - t)^2 and g[49] the summed squared residual, all
+// complete in every lane.
+__device__ __forceinline__ void wave_grad(const float (&p)[kNP], const float* u, const float* t, uint32_t m,
+                                          float (&g)[kNP + 1]) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const float scale = m ? 2.0f / (float)m : 0.0f;
 #pragma unroll
     for (int k = 0; k <= kNP; ++k) g[k] = 0.0f;
-    const float scale = m ? 2.0f / (float)m : 0.0f;
-    for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
-        const float uk = u[k];
+#pragma unroll 1
+    for (uint32_t j = lane; j < m; j += kWave) {
+        const float uk = u[j];
         float pre[16], h[16];
         float y = p[48];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            pre[j] = fmaf(p[j], uk, p[16 + j]);
-            h[j] = fmaxf(pre[j], 0.0f);
-            y = fmaf(p[32 + j], h[j], y);
+        for (int q = 0; q < 16; ++q) {
+            pre[q] = fmaf(p[q], uk, p[16 + q]);
+            h[q] = fmaxf(pre[q], 0.0f);
+            y = fmaf(p[32 + q], h[q], y);
         }
-        const float r = y - t[k];
+        const float r = y - t[j];
         g[kNP] = fmaf(r, r, g[kNP]);
         const float dy = r * scale;
         g[48] += dy;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            g[32 + j] = fmaf(dy, h[j], g[32 + j]);
-            const float dh = pre[j] > 0.0f ? dy * p[32 + j] : 0.0f;
-            g[j] = fmaf(dh, uk, g[j]);
-            g[16 + j] += dh;
+        for (int q = 0; q < 16; ++q) {
+            g[32 + q] = fmaf(dy, h[q], g[32 + q]);
+            const float dh = pre[q] > 0.0f ? dy * p[32 + q] : 0.0f;
+            g[q] = fmaf(dh, uk, g[q]);
+            g[16 + q] += dh;
         }
     }
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
-    for (int k = 0; k <= kNP; ++k) {
-        const float v = wave_sum_f32(g[k]);
-        if (lane == 0) red[w][k] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x <= kNP) {
-        float s = 0.0f;
-        for (int ww = 0; ww < (int)(blockDim.x / kWave); ++ww) s += red[ww][threadIdx.x];
-        out[threadIdx.x] = s;
-    }
-    __syncthreads();
+    for (int k = 0; k <= kNP; ++k) g[k] = wave_allsum(g[k]);
 }
 
 __device__ __forceinline__ uint32_t lower_bound_in(const uint32_t* K, uint32_t lo, uint32_t hi, uint32_t x) {
@@ -180,107 +192,112 @@ __device__ __forceinline__ uint32_t lower_bound_in(const uint32_t* K, uint32_t l
     return base;
 }
 
+__device__ __forceinline__ float bcast(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
 struct TrainCfg {
     uint32_t epochs, max_points;
     float lr, beta1, beta2;
 };
 
-__global__ void __launch_bounds__(kThreads) k_rmi_train(Pair2 P, TrainCfg tc) {
+constexpr int kTrainWaves = 2;
+
+__global__ void __launch_bounds__(kTrainWaves * kWave) k_rmi_train(Pair2 P, TrainCfg tc) {
+    __shared__ float pts[kTrainWaves][2][BITS_RMI_MAX_POINTS];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wv = threadIdx.x / kWave;
     const int a = blockIdx.y;
-    const uint32_t leaf = blockIdx.x;
+    const uint32_t leaf = blockIdx.x * kTrainWaves + wv;
     const uint32_t* K = P.keys[a];
     bits_rmi_leaf* L = &P.model[a]->leaf[leaf];
     const uint32_t rlo = P.bounds[a][leaf];
     const uint32_t cnt = P.bounds[a][leaf + 1] - rlo;
-    __shared__ float su[kMaxPoints], st[kMaxPoints];
-    __shared__ float prm[kNP];
-    __shared__ float gsum[kNP + 1];
-    __shared__ float red[kWaves][52];
-    __shared__ int32_t ered[2][kWaves];
-
+    uint32_t* Lw = reinterpret_cast<uint32_t*>(L);
     if (cnt == 0) {
-        for (int k = threadIdx.x; k < 64; k += blockDim.x) reinterpret_cast<uint32_t*>(L)[k] = 0u;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            L->kmin = 0xFFFFFFFFu;
-            L->kmax = 0u;
-            L->rlo = rlo;
-            L->cnt = 0u;
-        }
+        Lw[lane] = lane == 0 ? 0xFFFFFFFFu : lane == 2 ? rlo : 0u;
         return;
     }
     const uint32_t kmin = K[rlo], kmax = K[rlo + cnt - 1];
     const uint32_t span = kmax - kmin;
     const float kinv = 1.0f / (float)(span > 1u ? span : 1u);
     const uint32_t m = cnt < tc.max_points ? cnt : tc.max_points;
-    for (uint32_t j = threadIdx.x; j < m; j += blockDim.x) {
+
+    // training point j: the key at rank rlo + floor(j * cnt / m), target its
+    // lower-bound rank normalised to the leaf
+    float* u = pts[wv][0];
+    float* t = pts[wv][1];
+    for (uint32_t j = lane; j < m; j += kWave) {
         const uint32_t i = rlo + (uint32_t)(((uint64_t)j * cnt) / m);
         const uint32_t x = K[i];
-        const uint32_t lb = lower_bound_in(K, rlo, i, x);
-        su[j] = (float)(x - kmin) * kinv;
-        st[j] = (float)(lb - rlo) / (float)cnt;
+        u[j] = (float)(x - kmin) * kinv;
+        t[j] = (float)(lower_bound_in(K, rlo, i, x) - rlo) / (float)cnt;
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // Initial network: piecewise-linear interpolation of the sampled CDF at
     // 16 quantile knots (unit j is relu(u - knot_j), w2 the slope changes).
-    if (threadIdx.x == 0) {
+    float ku = 0.0f, kt = 0.0f;
+    if (lane <= 16) {
+        const uint32_t sidx = lane < 16 ? (uint32_t)(((uint64_t)lane * m) / 16u) : m - 1;
+        ku = u[sidx];
+        kt = t[sidx];
+    }
+    float p[kNP];
+    {
         float kn[17], tv[17];
-        for (int j = 0; j < 16; ++j) {
-            const uint32_t s = (uint32_t)(((uint64_t)j * m) / 16u);
-            kn[j] = su[s];
-            tv[j] = st[s];
+#pragma unroll
+        for (int j = 0; j < 17; ++j) {
+            kn[j] = bcast(ku, j);
+            tv[j] = bcast(kt, j);
         }
-        kn[16] = su[m - 1] > kn[15] ? su[m - 1] : kn[15] + 1e-3f;
-        tv[16] = st[m - 1];
+        if (!(kn[16] > kn[15])) kn[16] = kn[15] + 1e-3f;
         float prev = 0.0f;
+#pragma unroll
         for (int j = 0; j < 16; ++j) {
             const float du = fmaxf(kn[j + 1] - kn[j], 1e-6f);
-            float slope = (tv[j + 1] - tv[j]) / du;
-            slope = fminf(slope, 1e4f);
-            prm[j] = 1.0f;
-            prm[16 + j] = -kn[j];
-            prm[32 + j] = slope - prev;
+            const float slope = fminf((tv[j + 1] - tv[j]) / du, 1e4f);
+            p[j] = 1.0f;
+            p[16 + j] = -kn[j];
+            p[32 + j] = slope - prev;
             prev = slope;
         }
-        prm[48] = tv[0];
+        p[48] = tv[0];
     }
-    __syncthreads();
 
-    // Full-batch Adam; thread k < 49 owns parameter k and its moments.
+    // Full-batch Adam; lane k < 49 updates parameter k, then every lane
+    // reads the new parameters back from their owners.
+    float own = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kNP; ++j)
+        if (lane == (uint32_t)j) own = p[j];
     float mom = 0.0f, vel = 0.0f, b1t = 1.0f, b2t = 1.0f;
-    float last_loss = 0.0f;
+    float g[kNP + 1];
     for (uint32_t e = 0; e < tc.epochs; ++e) {
-        float p[kNP];
+        wave_grad(p, u, t, m, g);
+        float gk = 0.0f;
 #pragma unroll
-        for (int k = 0; k < kNP; ++k) p[k] = prm[k];
-        block_grad(su, st, m, p, red, gsum);
-        if (threadIdx.x < kNP) {
-            const float g = gsum[threadIdx.x];
-            mom = tc.beta1 * mom + (1.0f - tc.beta1) * g;
-            vel = tc.beta2 * vel + (1.0f - tc.beta2) * g * g;
-            b1t *= tc.beta1;
-            b2t *= tc.beta2;
-            const float mh = mom / (1.0f - b1t);
-            const float vh = vel / (1.0f - b2t);
-            prm[threadIdx.x] -= tc.lr * mh / (sqrtf(vh) + 1e-8f);
-        }
-        __syncthreads();
-    }
-    {
-        float p[kNP];
+        for (int j = 0; j < kNP; ++j)
+            if (lane == (uint32_t)j) gk = g[j];
+        mom = tc.beta1 * mom + (1.0f - tc.beta1) * gk;
+        vel = tc.beta2 * vel + (1.0f - tc.beta2) * gk * gk;
+        b1t *= tc.beta1;
+        b2t *= tc.beta2;
+        const float mh = mom / (1.0f - b1t);
+        const float vh = vel / (1.0f - b2t);
+        if (lane < (uint32_t)kNP) own -= tc.lr * mh / (sqrtf(vh) + 1e-8f);
 #pragma unroll
-        for (int k = 0; k < kNP; ++k) p[k] = prm[k];
-        block_grad(su, st, m, p, red, gsum);
-        last_loss = gsum[kNP] / (float)m;
+        for (int j = 0; j < kNP; ++j) p[j] = bcast(own, j);
     }
+    wave_grad(p, u, t, m, g);
+    const float last_loss = g[kNP] / (float)m;
 
-    // Error window over every key of the leaf (first occurrence of each value;
-    // x == kmin is answered without a search).
-    float p[kNP];
-#pragma unroll
-    for (int k = 0; k < kNP; ++k) p[k] = prm[k];
+    // Error window over every key of the leaf (first occurrence of each
+    // value; x == kmin is answered without a search), with the query-time
+    // prediction code.
     int32_t over = 0, under = 0;
-    for (uint32_t i = rlo + threadIdx.x; i < rlo + cnt; i += blockDim.x) {
+    for (uint32_t i = rlo + lane; i < rlo + cnt; i += kWave) {
         const uint32_t x = K[i];
         if (x == kmin) continue;
         if (K[i - 1] == x) continue;   // i > rlo here because x > kmin
@@ -290,40 +307,41 @@ __global__ void __launch_bounds__(kThreads) k_rmi_train(Pair2 P, TrainCfg tc) {
     }
     over = wave_max_i32(over);
     under = wave_max_i32(under);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane < (uint32_t)kNP) L->p[lane] = own;
     if (lane == 0) {
-        ered[0][w] = over;
-        ered[1][w] = under;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t o = 0, u = 0;
-        for (int k = 0; k < (int)(blockDim.x / kWave); ++k) {
-            o = max(o, ered[0][k]);
-            u = max(u, ered[1][k]);
-        }
         L->kmin = kmin;
         L->kmax = kmax;
         L->rlo = rlo;
         L->cnt = cnt;
         L->kinv = kinv;
-        L->err_lo = o;
-        L->err_hi = u;
+        L->err_lo = over;
+        L->err_hi = under;
         L->loss = last_loss;
     }
-    if (threadIdx.x < kNP) L->p[threadIdx.x] = prm[threadIdx.x];
 }
 
-__global__ void __launch_bounds__(kThreads) k_leaf_grad(const float* u, const float* t, uint32_t m,
-                                                         const float* params, float* grad, float* loss) {
-    __shared__ float red[kWaves][52];
-    __shared__ float gsum[kNP + 1];
-    float p[kNP];
+// Gradient entry point: the training kernel's own wave_grad on given points.
+__global__ void __launch_bounds__(kWave) k_leaf_grad(const float* u_in, const float* t_in, uint32_t m,
+                                                      const float* params, float* grad, float* loss) {
+    __shared__ float pts[2][BITS_RMI_MAX_POINTS];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    for (uint32_t j = lane; j < m; j += kWave) {
+        pts[0][j] = u_in[j];
+        pts[1][j] = t_in[j];
+    }
+    __syncthreads();
+    float p[kNP], g[kNP + 1];
 #pragma unroll
-    for (int k = 0; k < kNP; ++k) p[k] = params[k];
-    block_grad(u, t, m, p, red, gsum);
-    if (threadIdx.x < kNP) grad[threadIdx.x] = gsum[threadIdx.x];
-    if (threadIdx.x == 0) *loss = m ? gsum[kNP] / (float)m : 0.0f;
+    for (int j = 0; j < kNP; ++j) p[j] = params[j];
+    wave_grad(p, pts[0], pts[1], m, g);
+    if (lane < (uint32_t)kNP) {
+        float gk = 0.0f;
+#pragma unroll
+        for (int j = 0; j < kNP; ++j)
+            if (lane == (uint32_t)j) gk = g[j];
+        grad[lane] = gk;
+    }
+    if (lane == 0) *loss = m ? g[kNP] / (float)m : 0.0f;
 }
 
 }  // namespace
@@ -356,14 +374,14 @@ int launch_rmi_build2(const uint32_t* keys0, const uint32_t* keys1, uint64_t n, 
     if (gb < 1) gb = 1;
     hipLaunchKernelGGL(k_rmi_bounds, dim3(gb, 2), dim3(256), 0, s, P, n);
     TrainCfg tc{tr.epochs, tr.max_points, tr.lr, tr.beta1, tr.beta2};
-    hipLaunchKernelGGL(k_rmi_train, dim3(BITS_RMI_LEAVES, 2), dim3(kThreads), 0, s, P, tc);
+    hipLaunchKernelGGL(k_rmi_train, dim3(BITS_RMI_LEAVES / kTrainWaves, 2), dim3(kTrainWaves * kWave), 0, s, P, tc);
     BITS_CHECK_HIP(hipGetLastError());
     return BITS_OK;
 }
 
 hipError_t launch_rmi_leaf_grad(const float* u, const float* t, uint32_t m, const float* params, float* grad,
                                 float* loss, hipStream_t s) {
-    hipLaunchKernelGGL(k_leaf_grad, dim3(1), dim3(kThreads), 0, s, u, t, m, params, grad, loss);
+    hipLaunchKernelGGL(k_leaf_grad, dim3(1), dim3(kWave), 0, s, u, t, m, params, grad, loss);
     return hipGetLastError();
 }
 

@@ -1,13 +1,16 @@
 // Search kernels of libbits.so (gfx950): ICount (Algorithm 1) over the plain
 // index (LDS Eytzinger top tree + bisection of the bucket in HBM) or the
-// learned CDF index (route -> leaf model -> windowed bisection, verified),
-// the per-query / total counters (Algorithm 2), the Monte-Carlo loop of
-// Sec. 3.2 as one persistent launch, the batched-pairs kernel, projection and
-// small helpers.
+// learned CDF index (route -> leaf model -> one cooperative 128-byte line
+// probe at the predicted rank -> bisection of what is left of the error
+// window -> verification), the per-query / total counters (Algorithm 2),
+// the Monte-Carlo loop of Sec. 3.2 as one persistent launch, the
+// batched-pairs kernel, projection and small helpers.
 //
 // Every lane carries QPL queries, i.e. 2*QPL independent search chains (one
 // over B_S for a.end, one over B_E for a.start per query); the chains advance
-// in lock-step so their dependent loads overlap.
+// in lock-step so their dependent loads overlap.  Loads of the sorted arrays
+// that have no reuse are non-temporal, so the learned leaf records and the
+// shared top of the bisections stay in L2.
 #include <mutex>
 #include <unordered_map>
 
@@ -15,20 +18,47 @@
 
 namespace bits {
 
+using u32x4 = uint32_t __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ uint32_t ld_key(const uint32_t* p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ------------------------------------------------------------------ bisection
 // For each chain c: base[c] += #{K_c[base[c] .. base[c] + len[c]) < x[c]};
-// K_c is B_S for even c and B_E for odd c.  Leaves len[c] == 0.
+// K_c is B_S for even c and B_E for odd c.  Leaves len[c] == 0.  The first
+// `hot` probes are ordinary (cached) loads, later ones non-temporal.
 template <int NC>
 __device__ __forceinline__ void bisect_multi(const uint32_t* __restrict__ ks, const uint32_t* __restrict__ ke,
-                                             uint32_t (&base)[NC], uint32_t (&len)[NC], const uint32_t (&x)[NC]) {
-    while (true) {
+                                             uint32_t (&base)[NC], uint32_t (&len)[NC], const uint32_t (&x)[NC],
+                                             uint32_t hot) {
+    for (uint32_t step = 0;; ++step) {
         uint32_t v[NC];
         bool any = false;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const uint32_t* K = (c & 1) ? ke : ks;
             const uint32_t half = len[c] >> 1;
-            v[c] = half ? K[base[c] + half - 1] : 0u;
+            v[c] = 0u;
+            if (half) {
+                // a probe is streamed (non-temporal) unless it is one of the
+                // shared first probes or the range is down to ~2 lines, whose
+                // lines the next probes read again
+                if (step < hot || len[c] <= 64u)
+                    v[c] = ld_key<false>(K + base[c] + half - 1);
+                else
+                    v[c] = ld_key<true>(K + base[c] + half - 1);
+            }
             any |= half != 0;
         }
         if (!any) break;
@@ -45,7 +75,7 @@ __device__ __forceinline__ void bisect_multi(const uint32_t* __restrict__ ks, co
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const uint32_t* K = (c & 1) ? ke : ks;
-        v[c] = len[c] ? K[base[c]] : 0u;
+        v[c] = len[c] ? ld_key<false>(K + base[c]) : 0u;
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -54,9 +84,74 @@ __device__ __forceinline__ void bisect_multi(const uint32_t* __restrict__ ks, co
     }
 }
 
+// ------------------------------------------------------------------ line probe
+// For every lane's chains: cnt[c] = #{i in [la[c], lb[c]) : K_c[i] < x[c]},
+// where [la, lb) lies inside one 128-byte line (32 keys; the sorted arrays
+// are 256-byte aligned inside the reference block, which also covers the
+// tail of the last line).  The whole wave cooperates: 8 lanes read one line
+// with 16-byte loads, so one instruction fetches 8 whole lines; the 8 partial
+// counts are summed with lane exchanges.  `scr` is this wave's LDS scratch of
+// 4 * NC * 64 words.  Must be called by all 64 lanes.
+template <int NC>
+__device__ __forceinline__ void probe_lines(const uint32_t* __restrict__ ks, const uint32_t* __restrict__ ke,
+                                            const uint32_t (&la)[NC], const uint32_t (&lb)[NC],
+                                            const uint32_t (&x)[NC], uint32_t (&cnt)[NC], uint32_t* scr) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        scr[(4 * c + 0) * kWave + lane] = la[c];
+        scr[(4 * c + 1) * kWave + lane] = lb[c];
+        scr[(4 * c + 2) * kWave + lane] = x[c];
+    }
+    wave_lds_sync();
+    const uint32_t sub = lane & 7u, grp = lane >> 3;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const uint32_t* K = (c & 1) ? ke : ks;
+        u32x4 v[8];
+        uint32_t a[8], b[8], xx[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t owner = (uint32_t)j * 8u + grp;
+            a[j] = scr[(4 * c + 0) * kWave + owner];
+            b[j] = scr[(4 * c + 1) * kWave + owner];
+            xx[j] = scr[(4 * c + 2) * kWave + owner];
+            const uint32_t i0 = (a[j] & ~31u) + 4u * sub;
+            v[j] = (a[j] < b[j]) ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(K + i0)) : u32x4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t owner = (uint32_t)j * 8u + grp;
+            const uint32_t i0 = (a[j] & ~31u) + 4u * sub;
+            uint32_t n = 0;
+            if (a[j] < b[j]) {
+                n += (i0 + 0 >= a[j] && i0 + 0 < b[j] && v[j].x < xx[j]) ? 1u : 0u;
+                n += (i0 + 1 >= a[j] && i0 + 1 < b[j] && v[j].y < xx[j]) ? 1u : 0u;
+                n += (i0 + 2 >= a[j] && i0 + 2 < b[j] && v[j].z < xx[j]) ? 1u : 0u;
+                n += (i0 + 3 >= a[j] && i0 + 3 < b[j] && v[j].w < xx[j]) ? 1u : 0u;
+            }
+            n += __shfl_xor(n, 1);
+            n += __shfl_xor(n, 2);
+            n += __shfl_xor(n, 4);
+            if (sub == 0) scr[(4 * c + 3) * kWave + owner] = n;
+        }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) cnt[c] = scr[(4 * c + 3) * kWave + lane];
+    wave_lds_sync();
+}
+
+// Words of LDS probe scratch per wave for QPL queries per lane.
+__host__ __device__ constexpr uint32_t probe_scratch_words(int qpl) { return 4u * 2u * (uint32_t)qpl * kWave; }
+
 // ------------------------------------------------------------------ ICount
 // first = #{B_S <= a.end} = #{B_S < a.end + 1}; last = #{B_E < a.start};
 // count = first - last (Sec. 2.1).  a.end == 2^32-1 means first = |B|.
+
+// Bisection probes kept in L2 on the plain path: the first few probes of a
+// bucket are shared by every query landing in it.
+constexpr uint32_t kPlainHotSteps = 3;
 
 template <int QPL>
 __device__ __forceinline__ void icount_plain(const SearchArgs& sa, const uint32_t* lds,
@@ -92,7 +187,7 @@ __device__ __forceinline__ void icount_plain(const SearchArgs& sa, const uint32_
             len[c] = sa.n;
         }
     }
-    bisect_multi<NC>(sa.bs, sa.be, base, len, x);
+    bisect_multi<NC>(sa.bs, sa.be, base, len, x, kPlainHotSteps);
 #pragma unroll
     for (int q = 0; q < QPL; ++q) {
         const uint32_t first = (ae[q] == 0xFFFFFFFFu) ? sa.n : base[2 * q];
@@ -100,11 +195,12 @@ __device__ __forceinline__ void icount_plain(const SearchArgs& sa, const uint32_
     }
 }
 
+// Learned path.  Must be called by all 64 lanes of the wave (line probe).
 template <int QPL>
-__device__ __forceinline__ void icount_learned(const SearchArgs& sa, const uint32_t (&as)[QPL],
+__device__ __forceinline__ void icount_learned(const SearchArgs& sa, uint32_t* scr, const uint32_t (&as)[QPL],
                                                const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL]) {
     constexpr int NC = 2 * QPL;
-    uint32_t x[NC], base[NC], len[NC], wl[NC], wr[NC], rlo[NC], rhi[NC];
+    uint32_t x[NC], base[NC], len[NC], wl[NC], wr[NC], rlo[NC], rhi[NC], pa[NC], pb[NC], pc[NC];
     bool win[NC];
 #pragma unroll
     for (int q = 0; q < QPL; ++q) {
@@ -123,6 +219,8 @@ __device__ __forceinline__ void icount_learned(const SearchArgs& sa, const uint3
         win[c] = false;
         base[c] = rlo[c];
         len[c] = 0;
+        pa[c] = pb[c] = 0;
+        wl[c] = wr[c] = 0;
         if (x[c] > h0.y) {
             base[c] = rhi[c];
         } else if (x[c] > h0.x) {
@@ -133,11 +231,30 @@ __device__ __forceinline__ void icount_learned(const SearchArgs& sa, const uint3
             wr[c] = (uint32_t)min(hi, (int32_t)rhi[c]);
             if (wr[c] < wl[c]) wr[c] = wl[c];
             base[c] = wl[c];
-            len[c] = wr[c] - wl[c];
             win[c] = true;
+            if (wr[c] > wl[c]) {
+                const uint32_t p = min(max((uint32_t)max(pred, 0), wl[c]), wr[c] - 1u);
+                const uint32_t line = p & ~31u;
+                pa[c] = max(line, wl[c]);
+                pb[c] = min(line + 32u, wr[c]);
+            }
         }
     }
-    bisect_multi<NC>(sa.bs, sa.be, base, len, x);
+    probe_lines<NC>(sa.bs, sa.be, pa, pb, x, pc, scr);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (!win[c] || pb[c] == pa[c]) continue;
+        if (pc[c] > 0 && pc[c] < pb[c] - pa[c]) {
+            base[c] = pa[c] + pc[c];
+        } else if (pc[c] == 0) {
+            base[c] = wl[c];
+            len[c] = pa[c] - wl[c];
+        } else {
+            base[c] = pb[c];
+            len[c] = wr[c] - pb[c];
+        }
+    }
+    bisect_multi<NC>(sa.bs, sa.be, base, len, x, 0u);
     bool any_fb = false;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -145,8 +262,8 @@ __device__ __forceinline__ void icount_learned(const SearchArgs& sa, const uint3
         const uint32_t* K = (c & 1) ? sa.be : sa.bs;
         const uint32_t r = base[c];
         bool ok = true;
-        if (r == wl[c] && wl[c] != rlo[c]) ok = K[wl[c] - 1] < x[c];
-        if (r == wr[c] && wr[c] != rhi[c]) ok = ok && (K[wr[c]] >= x[c]);
+        if (r == wl[c] && wl[c] != rlo[c]) ok = ld_key<true>(K + wl[c] - 1) < x[c];
+        if (r == wr[c] && wr[c] != rhi[c]) ok = ok && (ld_key<true>(K + wr[c]) >= x[c]);
         if (!ok) {
             base[c] = rlo[c];
             len[c] = rhi[c] - rlo[c];
@@ -154,7 +271,7 @@ __device__ __forceinline__ void icount_learned(const SearchArgs& sa, const uint3
             atomicAdd(sa.fallbacks, 1ull);
         }
     }
-    if (any_fb) bisect_multi<NC>(sa.bs, sa.be, base, len, x);
+    if (any_fb) bisect_multi<NC>(sa.bs, sa.be, base, len, x, 0u);
 #pragma unroll
     for (int q = 0; q < QPL; ++q) {
         const uint32_t first = (ae[q] == 0xFFFFFFFFu) ? sa.n : base[2 * q];
@@ -163,12 +280,18 @@ __device__ __forceinline__ void icount_learned(const SearchArgs& sa, const uint3
 }
 
 template <int QPL, bool LEARNED>
-__device__ __forceinline__ void icount(const SearchArgs& sa, const uint32_t* lds, const uint32_t (&as)[QPL],
+__device__ __forceinline__ void icount(const SearchArgs& sa, uint32_t* lds, const uint32_t (&as)[QPL],
                                        const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL]) {
     if constexpr (LEARNED)
-        icount_learned<QPL>(sa, as, ae, cnt);
+        icount_learned<QPL>(sa, lds + (threadIdx.x / kWave) * probe_scratch_words(QPL), as, ae, cnt);
     else
         icount_plain<QPL>(sa, lds, as, ae, cnt);
+}
+
+// Dynamic LDS of a search kernel: the top trees (plain) or the per-wave probe
+// scratch (learned).
+__host__ __device__ constexpr size_t search_lds_bytes(bool learned, uint32_t depth, int qpl, uint32_t block) {
+    return learned ? (size_t)(block / kWave) * probe_scratch_words(qpl) * 4u : (size_t)tree_lds_words(depth) * 4u;
 }
 
 // ------------------------------------------------------------------ counting kernel
@@ -221,55 +344,83 @@ __global__ void __launch_bounds__(1024) k_count(SearchArgs sa, const uint32_t* _
 }
 
 // ------------------------------------------------------------------ Monte-Carlo
-// Work item = (shuffle s, tile of blockDim*QPL queries); items are walked by a
-// persistent grid.  Query i of shuffle s starts at off_i + floor(u * span_i /
-// 2^64), u = the first two Philox words of counter g = (s0 + s) * na + i.
-// OBSERVED counts the unshuffled queries instead (same exclusion of queries
-// with span 0, i.e. outside their chromosome).
+// Work item = (tile of blockDim*QPL queries, chunk of consecutive shuffles);
+// items are walked by a persistent grid.  A workgroup reads its tile's
+// per-query table once per item and runs every shuffle of the chunk on it.
+// Query i of shuffle s starts at off_i + floor(u * span_i / 2^64), u = the
+// first two Philox words of counter g = (s0 + s) * na + i.  Per-shuffle wave
+// sums are added in LDS and flushed with one global atomic per shuffle per
+// item.  OBSERVED counts the unshuffled queries instead (same exclusion of
+// queries with span 0, i.e. outside their chromosome).
+constexpr uint32_t kMaxChunk = 64;
 
 template <int QPL, bool LEARNED, bool OBSERVED>
 __global__ void __launch_bounds__(1024)
     k_mc(SearchArgs sa, const uint32_t* __restrict__ a_start, const uint32_t* __restrict__ a_end,
          const uint32_t* __restrict__ off, const uint32_t* __restrict__ span, const uint32_t* __restrict__ len,
-         uint64_t na, uint64_t seed, uint64_t s0, uint64_t nshuf, uint64_t tiles_per_shuf,
+         uint64_t na, uint64_t seed, uint64_t s0, uint64_t nshuf, uint64_t tiles, uint32_t chunk,
          unsigned long long* __restrict__ totals) {
     extern __shared__ uint32_t lds[];
-    if (!LEARNED) {
-        stage_tree(lds, sa.tree, sa.tree_stride, sa.depth);
-        __syncthreads();
-    }
+    __shared__ unsigned long long acc[kMaxChunk];
+    if (!LEARNED) stage_tree(lds, sa.tree, sa.tree_stride, sa.depth);
+    for (uint32_t k = threadIdx.x; k < kMaxChunk; k += blockDim.x) acc[k] = 0ull;
+    __syncthreads();
     const uint64_t tile = (uint64_t)blockDim.x * QPL;
-    const uint64_t nitems = nshuf * tiles_per_shuf;
+    const uint64_t nchunks = (nshuf + chunk - 1) / chunk;
+    const uint64_t nitems = tiles * nchunks;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const uint64_t s = it / tiles_per_shuf;
-        const uint64_t t = it - s * tiles_per_shuf;
-        uint32_t as[QPL], ae[QPL], cnt[QPL];
+        const uint64_t kc = it / tiles;
+        const uint64_t t = it - kc * tiles;
+        uint32_t qo[QPL], qs[QPL], ql[QPL];
+        uint64_t qi[QPL];
         bool valid[QPL];
 #pragma unroll
         for (int q = 0; q < QPL; ++q) {
-            const uint64_t i = t * tile + (uint64_t)q * blockDim.x + threadIdx.x;
-            const uint32_t sp = i < na ? span[i] : 0u;
-            valid[q] = sp != 0u;
+            qi[q] = t * tile + (uint64_t)q * blockDim.x + threadIdx.x;
+            qs[q] = qi[q] < na ? span[qi[q]] : 0u;
+            valid[q] = qs[q] != 0u;
             if (OBSERVED) {
-                as[q] = valid[q] ? a_start[i] : 0u;
-                ae[q] = valid[q] ? a_end[i] : 0u;
+                qo[q] = valid[q] ? a_start[qi[q]] : 0u;
+                ql[q] = valid[q] ? a_end[qi[q]] : 0u;
             } else {
-                const uint64_t g = (s0 + s) * na + i;
-                uint32_t c0 = (uint32_t)g, c1 = (uint32_t)(g >> 32), c2 = 0u, c3 = 0u;
-                philox4x32_10(c0, c1, c2, c3, k0, k1);
-                const uint64_t u = ((uint64_t)c1 << 32) | c0;
-                const uint32_t local = (uint32_t)__umul64hi(u, (uint64_t)sp);
-                as[q] = valid[q] ? off[i] + local : 0u;
-                ae[q] = valid[q] ? as[q] + len[i] - 1u : 0u;
+                qo[q] = valid[q] ? off[qi[q]] : 0u;
+                ql[q] = valid[q] ? len[qi[q]] : 1u;
             }
         }
-        icount<QPL, LEARNED>(sa, lds, as, ae, cnt);
-        uint64_t acc = 0;
+        const uint64_t sb = kc * chunk;
+        const uint64_t se = min(nshuf, sb + chunk);
+        for (uint64_t s = sb; s < se; ++s) {
+            uint32_t as[QPL], ae[QPL], cnt[QPL];
 #pragma unroll
-        for (int q = 0; q < QPL; ++q) acc += valid[q] ? cnt[q] : 0u;
-        acc = wave_sum_u64(acc);
-        if ((threadIdx.x & (kWave - 1)) == 0 && acc) atomicAdd(totals + s, (unsigned long long)acc);
+            for (int q = 0; q < QPL; ++q) {
+                if (OBSERVED) {
+                    as[q] = qo[q];
+                    ae[q] = ql[q];
+                } else {
+                    const uint64_t g = (s0 + s) * na + qi[q];
+                    uint32_t c0 = (uint32_t)g, c1 = (uint32_t)(g >> 32), c2 = 0u, c3 = 0u;
+                    philox4x32_10(c0, c1, c2, c3, k0, k1);
+                    const uint64_t u = ((uint64_t)c1 << 32) | c0;
+                    const uint32_t local = (uint32_t)__umul64hi(u, (uint64_t)qs[q]);
+                    as[q] = valid[q] ? qo[q] + local : 0u;
+                    ae[q] = valid[q] ? as[q] + ql[q] - 1u : 0u;
+                }
+            }
+            icount<QPL, LEARNED>(sa, lds, as, ae, cnt);
+            uint64_t sum = 0;
+#pragma unroll
+            for (int q = 0; q < QPL; ++q) sum += valid[q] ? cnt[q] : 0u;
+            sum = wave_sum_u64(sum);
+            if ((threadIdx.x & (kWave - 1)) == 0 && sum) atomicAdd(&acc[s - sb], (unsigned long long)sum);
+        }
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < (uint32_t)(se - sb); k += blockDim.x) {
+            const unsigned long long v = acc[k];
+            if (v) atomicAdd(totals + sb + k, v);
+            acc[k] = 0ull;
+        }
+        __syncthreads();
     }
 }
 
@@ -486,7 +637,7 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
 template <int QPL, bool LEARNED>
 static hipError_t launch_count_t(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
                                  uint64_t na, uint32_t* counts, unsigned long long* total, hipStream_t s) {
-    const size_t lds = LEARNED ? 0 : tree_lds_words(sa.depth) * sizeof(uint32_t);
+    const size_t lds = search_lds_bytes(LEARNED, sa.depth, QPL, cfg.block);
     const uint64_t tile = (uint64_t)cfg.block * QPL;
     const void* kern = (const void*)k_count<QPL, LEARNED>;
     const uint32_t grid = persistent_grid(kern, cfg, lds, (na + tile - 1) / tile);
@@ -539,20 +690,23 @@ static hipError_t launch_mc_t(const SearchArgs& sa, const LaunchCfg& cfg, const 
                               const uint32_t* off, const uint32_t* span, const uint32_t* len, uint64_t na,
                               uint64_t seed, uint64_t s0, uint64_t nshuf, unsigned long long* totals,
                               unsigned long long* observed, hipStream_t s) {
-    const size_t lds = LEARNED ? 0 : tree_lds_words(sa.depth) * sizeof(uint32_t);
+    const size_t lds = search_lds_bytes(LEARNED, sa.depth, QPL, cfg.block);
     const uint64_t tile = (uint64_t)cfg.block * QPL;
     const uint64_t tps = (na + tile - 1) / tile;
     if (observed) {
         const void* ko = (const void*)k_mc<QPL, LEARNED, true>;
         const uint32_t go = persistent_grid(ko, cfg, lds, tps);
         hipLaunchKernelGGL((k_mc<QPL, LEARNED, true>), dim3(go), dim3(cfg.block), lds, s, sa, as, ae, off, span,
-                           len, na, seed, s0, (uint64_t)1, tps, observed);
+                           len, na, seed, s0, (uint64_t)1, tps, 1u, observed);
     }
     if (nshuf) {
         const void* km = (const void*)k_mc<QPL, LEARNED, false>;
         const uint32_t gm = persistent_grid(km, cfg, lds, nshuf * tps);
+        // shuffles per work item: as many as keep >= 8 items per workgroup
+        uint32_t chunk = kMaxChunk;
+        while (chunk > 1 && tps * ((nshuf + chunk - 1) / chunk) < 8ull * gm) chunk >>= 1;
         hipLaunchKernelGGL((k_mc<QPL, LEARNED, false>), dim3(gm), dim3(cfg.block), lds, s, sa, as, ae, off, span,
-                           len, na, seed, s0, nshuf, tps, totals);
+                           len, na, seed, s0, nshuf, tps, chunk, totals);
     }
     return hipGetLastError();
 }

@@ -240,7 +240,7 @@ def test_batch_pairs_graph_replay():
 def test_learned_gradient_matches_oracle():
     note("case: leaf gradient")
     r = np.random.default_rng(12)
-    for m in (1, 100, 4096):
+    for m in (1, 100, 2048):
         p = r.normal(0, 1, 49).astype(np.float32)
         u = r.uniform(0, 1, m).astype(np.float32)
         t = np.sort(r.uniform(0, 1, m)).astype(np.float32)
