@@ -66,7 +66,8 @@ typedef enum bits_status {
 /* Launch shape of the search kernels.  A NULL bits_launch* means the
  * library defaults; bits_autotune_count picks one by timing. */
 typedef struct bits_launch {
-    uint32_t block;   /* threads per workgroup: 256, 512 or 1024 (0 = default 1024) */
+    uint32_t block;   /* threads per workgroup: 256, 512 or 1024 (0 = default 1024); the learned
+                         path uses a smaller one when its LDS scratch would not fit */
     uint32_t qpl;     /* queries interleaved per lane: 1, 2 or 4 (0 = default 2) */
     uint32_t depth;   /* top-tree levels searched from LDS, <= the reference's depth
                          (0xFFFFFFFF = the reference's depth; 0 = no LDS tree) */
@@ -80,8 +81,9 @@ typedef struct bits_launch {
  *   status[64]   uint32: [0] status bits, [2..3] uint64 learned-path fallbacks
  *   tree         uint32[2][2^depth]: Eytzinger splitters of B_S then B_E,
  *                node k (1-based BFS order) at [k]; entry 0 unused
- *   rmi          (learned only) 2 x bits_rmi_model
- *   bs, be       uint32[n] each: sorted B_S and B_E (Sec. 2.1, Algorithm 2) */
+ *   rmi          (learned only) 2 x bits_rmi_model (128-byte header + 4096 leaves)
+ *   bs, be       uint32[n] each: sorted B_S and B_E (Sec. 2.1, Algorithm 2); the rest
+ *                of each array's last 128-byte line is filled with 0xFFFFFFFF */
 typedef struct bits_ref {
     uint64_t n;          /* |B|, < 2^32 */
     uint32_t depth;      /* top-tree depth built: min(requested, floor(log2 n)) */
@@ -95,16 +97,23 @@ typedef struct bits_ref {
     size_t block_bytes;
 } bits_ref;
 
-/* One leaf of the learned CDF index (device layout, 256 bytes).  Keys routed
- * to the leaf are the contiguous sorted range [rlo, rlo + cnt). */
+/* One leaf of the learned CDF index: one 128-byte line.  Keys routed to the
+ * leaf are the contiguous sorted range [rlo, rlo + cnt).  The model is
+ *   y(u) = b2 + sum_j w2_j relu(w1_j u + b1_j),  j = 0..15,
+ * u = (x - kmin) * kinv, predicted rank rlo + clamp(rint(y * cnt), 0, cnt).
+ * w1, b1, w2 are stored as IEEE binary16 (fp32 arithmetic); kinv and b2 as
+ * fp32 bit patterns.  The record is laid out for 4 lanes reading it with two
+ * 16-byte loads each: lane q takes a[q] (bytes 16q..16q+15) and b[q]
+ * (bytes 64+16q..), i.e. header words h[] and hidden units 4q..4q+3.
+ *   a[0].h = {kmin, kmax}      kmin = 0xFFFFFFFF for an empty leaf
+ *   a[1].h = {rlo, cnt}
+ *   a[2].h = {kinv, b2}        kinv = 1 / max(1, kmax - kmin)
+ *   a[3].h = {err_lo | err_hi << 16, loss}
+ * err_lo / err_hi: largest over- / under-prediction of the rank over the
+ * leaf's keys (capped at 65535; a capped window only causes a fallback). */
 typedef struct bits_rmi_leaf {
-    uint32_t kmin, kmax;     /* smallest / largest key of the leaf (kmin = 0xFFFFFFFF if empty) */
-    uint32_t rlo, cnt;       /* first rank and number of keys */
-    float kinv;              /* 1 / max(1, kmax - kmin) */
-    int32_t err_lo, err_hi;  /* max over-/under-prediction of the rank over the leaf's keys */
-    float loss;              /* final training loss (mean squared, normalised ranks) */
-    float p[BITS_RMI_PARAMS];/* w1[16], b1[16], w2[16], b2 */
-    uint32_t pad[7];
+    struct { uint32_t h[2]; uint16_t w1[4]; } a[4];
+    struct { uint16_t b1[4]; uint16_t w2[4]; } b[4];
 } bits_rmi_leaf;
 
 /* Learned CDF index of one sorted array: root line routing to 4096 leaves. */
@@ -112,14 +121,14 @@ typedef struct bits_rmi_model {
     float root_a, root_b;    /* leaf = clamp(floor(fmaf(root_a, (float)x, root_b)), 0, 4095) */
     double fit_a, fit_b;     /* least-squares line rank ~ fit_a * key + fit_b (fp64) */
     uint64_t n;
-    uint32_t pad[56];
+    uint32_t pad[24];
     bits_rmi_leaf leaf[BITS_RMI_LEAVES];
 } bits_rmi_model;
 
 /* Training settings for the learned index (NULL = defaults). */
 typedef struct bits_train {
     uint32_t epochs;      /* full-batch Adam steps per leaf (default 300; 0 = init only) */
-    uint32_t max_points;  /* training points per leaf, stride-sampled (default and max 2048) */
+    uint32_t max_points;  /* training points per leaf, stride-sampled (default 256, max 2048) */
     float lr;             /* Adam step size (default 2e-3) */
     float beta1, beta2;   /* Adam moments (defaults 0.9, 0.999) */
 } bits_train;
@@ -309,6 +318,17 @@ int bits_autotune_count(const bits_ref *ref, const uint32_t *d_a_start, const ui
  *   d_grad        device float[49];  d_loss device float[1] */
 int bits_rmi_leaf_grad(const float *d_u, const float *d_t, uint32_t m, const float *d_params,
                        float *d_grad, float *d_loss, void *stream);
+
+/* Search window of the learned index, computed by the same device code the
+ * learned searches run (route, leaf model, error window): for each key
+ * d_x[i], the window [d_lo[i], d_hi[i]] of ranks in which
+ * lower_bound(array, d_x[i]) is searched, or d_lo[i] = d_hi[i] = that rank
+ * when the leaf resolves it directly (x <= the leaf's smallest key or > its
+ * largest).  which: 0 = sorted starts, 1 = sorted ends.  For every key of
+ * the array the window holds its rank; other queries are verified by the
+ * search itself.  The reference must be learned and non-empty. */
+int bits_rmi_window(const bits_ref *ref, uint32_t which, const uint32_t *d_x, uint64_t n, uint32_t *d_lo,
+                    uint32_t *d_hi, void *stream);
 
 #ifdef __cplusplus
 }

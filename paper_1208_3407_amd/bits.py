@@ -17,7 +17,8 @@ from typing import List, Optional, Sequence, Tuple
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbits.so")
+# BITS_LIBRARY may name another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("BITS_LIBRARY") or os.path.join(_HERE, "libbits.so")
 
 BITS_OK = 0
 BITS_FLAG_INTERVAL = 0x1
@@ -51,9 +52,9 @@ class bits_rmi_stats(ctypes.Structure):
                 ("mean_loss", ctypes.c_double), ("fallbacks", _u64)]
 
 
-# byte layout of one learned model (bits_rmi_model): 256-byte header + 4096 leaves of 256 bytes
-RMI_HEADER_BYTES = 256
-RMI_LEAF_BYTES = 256
+# byte layout of one learned model (bits_rmi_model): 128-byte header + 4096 leaves of 128 bytes
+RMI_HEADER_BYTES = 128
+RMI_LEAF_BYTES = 128
 RMI_LEAVES = 4096
 RMI_MODEL_BYTES = RMI_HEADER_BYTES + RMI_LEAVES * RMI_LEAF_BYTES
 
@@ -95,6 +96,7 @@ def _load():
         "bits_autotune_count": ([P(bits_ref), _vp, _vp, _u64, _vp, _u32, P(bits_launch), P(ctypes.c_float), _vp],
                                 ctypes.c_int),
         "bits_rmi_leaf_grad": ([_vp, _vp, _u32, _vp, _vp, _vp, _vp], ctypes.c_int),
+        "bits_rmi_window": ([P(bits_ref), _u32, _vp, _u64, _vp, _vp, _vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -247,7 +249,7 @@ def bits_ref_init(n: int, depth: int = BITS_MAX_DEPTH, learned: bool = False, bl
 def _train(train: Optional[dict]):
     if train is None:
         return None
-    t = bits_train(int(train.get("epochs", 300)), int(train.get("max_points", 2048)), float(train.get("lr", 2e-3)),
+    t = bits_train(int(train.get("epochs", 300)), int(train.get("max_points", 256)), float(train.get("lr", 2e-3)),
                    float(train.get("beta1", 0.9)), float(train.get("beta2", 0.999)))
     return ctypes.byref(t)
 
@@ -464,3 +466,14 @@ def bits_rmi_leaf_grad(u: torch.Tensor, t: torch.Tensor, params: torch.Tensor, s
     _check(_lib.bits_rmi_leaf_grad(_ptr(u), _ptr(t), u.numel(), _ptr(params), _ptr(grad), _ptr(loss),
                                    _stream(stream)), "bits_rmi_leaf_grad")
     return grad, loss
+
+
+def bits_rmi_window(ref: Ref, which: int, x, stream=None):
+    """Learned-path search windows [lo, hi] for keys x (device code of the searches)."""
+    dev = _device()
+    x = _u32_dev(x, "x")
+    lo = torch.empty(x.numel(), dtype=torch.uint32, device=dev)
+    hi = torch.empty(x.numel(), dtype=torch.uint32, device=dev)
+    _check(_lib.bits_rmi_window(ctypes.byref(ref.c), int(which), _ptr(x), x.numel(), _ptr(lo), _ptr(hi),
+                                _stream(stream)), "bits_rmi_window")
+    return lo, hi

@@ -52,7 +52,7 @@ bool ref_ok(const bits_ref* r) {
 }
 
 bits_train train_defaults(const bits_train* t) {
-    bits_train d{300u, BITS_RMI_MAX_POINTS, 2e-3f, 0.9f, 0.999f};
+    bits_train d{300u, 256u, 2e-3f, 0.9f, 0.999f};
     if (!t) return d;
     bits_train r = *t;
     if (r.max_points == 0 || r.max_points > BITS_RMI_MAX_POINTS) r.max_points = BITS_RMI_MAX_POINTS;
@@ -85,6 +85,11 @@ int resolve_launch(const bits_ref* ref, const bits_launch* in, LaunchCfg* out) {
     if (c.path == BITS_PATH_LEARNED && !ref->learned) return BITS_E_ARG;
     if (c.block != 256 && c.block != 512 && c.block != 1024) return BITS_E_ARG;
     if (c.qpl != 1 && c.qpl != 2 && c.qpl != 4) return BITS_E_ARG;
+    // the learned path's per-wave scratch grows with qpl: step the block down
+    // until one workgroup's scratch fits the device's LDS
+    while (c.path == BITS_PATH_LEARNED && c.block > 256 &&
+           search_lds_bytes(true, 0, (int)c.qpl, c.block) + 1024 > device_lds_per_block())
+        c.block >>= 1;
     *out = c;
     return BITS_OK;
 }
@@ -203,6 +208,10 @@ int bits_sort_refs_workspace(const uint64_t* n, uint32_t n_ref, size_t* bytes) {
 static int finish_ref(const bits_ref* r, const bits_train& tr, void* ws, hipStream_t s) {
     BITS_CHECK_HIP(launch_fill_u32(r->status, kStatusBytes / 4, 0u, s));
     if (r->n) {
+        // keys past n up to the end of the last 128-byte line read as +inf
+        const uint64_t pad = ((r->n + 31) & ~31ull) - r->n;
+        BITS_CHECK_HIP(launch_fill_u32(r->bs + r->n, pad, 0xFFFFFFFFu, s));
+        BITS_CHECK_HIP(launch_fill_u32(r->be + r->n, pad, 0xFFFFFFFFu, s));
         BITS_CHECK_HIP(launch_build_tree(r->bs, r->n, r->depth, r->tree, s));
         BITS_CHECK_HIP(launch_build_tree(r->be, r->n, r->depth, r->tree + ((size_t)1 << r->depth), s));
     } else {
@@ -278,13 +287,16 @@ int bits_rmi_info(const bits_ref* ref, void* stream, bits_rmi_stats* out) {
     for (int a = 0; a < 2; ++a)
         for (uint32_t l = 0; l < BITS_RMI_LEAVES; ++l) {
             const bits_rmi_leaf& L = host[a].leaf[l];
-            if (L.cnt == 0) {
+            if (L.a[1].h[1] == 0) {   // cnt
                 ++empty;
                 continue;
             }
-            const uint32_t w = (uint32_t)(L.err_lo + L.err_hi + 1);
+            const uint32_t err = L.a[3].h[0];
+            const uint32_t w = (err & 0xFFFFu) + (err >> 16) + 1u;
+            float loss;
+            memcpy(&loss, &L.a[3].h[1], sizeof(loss));
             wsum += w;
-            lsum += L.loss;
+            lsum += loss;
             wmax = std::max(wmax, w);
             ++nonempty;
         }
@@ -578,6 +590,15 @@ int bits_autotune_count(const bits_ref* ref, const uint32_t* d_a_start, const ui
     if (rc != BITS_OK) return rc;
     *best = bl;
     *best_ms = bestt;
+    return BITS_OK;
+}
+
+int bits_rmi_window(const bits_ref* ref, uint32_t which, const uint32_t* d_x, uint64_t n, uint32_t* d_lo,
+                    uint32_t* d_hi, void* stream) {
+    if (!ref_ok(ref) || !ref->learned || which > 1 || (n && (!d_x || !d_lo || !d_hi))) return BITS_E_ARG;
+    if (!ref->n) return BITS_E_ARG;
+    LaunchCfg cfg{256u, 1u, 0u, 0u, BITS_PATH_LEARNED};
+    BITS_CHECK_HIP(launch_rmi_window(make_search_args(ref, cfg), which, d_x, n, d_lo, d_hi, (hipStream_t)stream));
     return BITS_OK;
 }
 

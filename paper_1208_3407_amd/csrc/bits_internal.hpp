@@ -82,6 +82,17 @@ struct SearchArgs {
 // Number of LDS words a search kernel stages for depth d (both arrays).
 __host__ __device__ constexpr uint32_t tree_lds_words(uint32_t d) { return d ? (2u << d) : 0u; }
 
+// LDS scratch of the learned search per chain: (leaf, x) of 64 owners, then
+// 6 result words per owner; per wave: 2 * QPL chains.
+constexpr uint32_t kLeafScr = 2 * kWave + 6 * kWave;
+__host__ __device__ constexpr uint32_t probe_scratch_words(int qpl) { return 2u * (uint32_t)qpl * kLeafScr; }
+
+// Dynamic LDS of a search kernel: the top trees (plain) or the per-wave
+// scratch (learned).
+__host__ __device__ constexpr size_t search_lds_bytes(bool learned, uint32_t depth, int qpl, uint32_t block) {
+    return learned ? (size_t)(block / kWave) * probe_scratch_words(qpl) * 4u : (size_t)tree_lds_words(depth) * 4u;
+}
+
 // Copy the first 2^d - 1 nodes of both trees into LDS: lds[0..2^d) starts,
 // lds[2^d..2^(d+1)) ends, 1-based BFS order (slot 0 unused).
 __device__ __forceinline__ void stage_tree(uint32_t* lds, const uint32_t* tree, uint32_t stride, uint32_t d) {
@@ -101,20 +112,40 @@ __device__ __forceinline__ uint32_t rmi_route(float a, float b, uint32_t x) {
     return (uint32_t)r;
 }
 
-// Rank offset predicted inside a leaf for a key x with kmin <= x (dx = x - kmin).
-// The same arithmetic is used when the error windows are measured and when
-// queries are answered.
-__device__ __forceinline__ int32_t rmi_pred_offset(const float* p, uint32_t cnt, float kinv, uint32_t dx) {
-    const float u = (float)dx * kinv;
-    float y = p[48];
+// Leaf prediction, in one fixed arithmetic order shared by the error-window
+// measurement (sequential, rmi_pred_offset) and the queries (4 lanes per
+// leaf, rmi_quad_partial + two lane-pair additions):
+//   h_j = max(fma(w1_j, u, b1_j), 0),  s_q = fma-chain over j = 4q..4q+3 of w2_j h_j,
+//   y   = b2 + ((s_0 + s_1) + (s_2 + s_3)).
+__device__ __forceinline__ float rmi_quad_partial(const float* w1, const float* b1, const float* w2, float u) {
+    float s = 0.0f;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const float h = fmaxf(fmaf(p[j], u, p[16 + j]), 0.0f);
-        y = fmaf(p[32 + j], h, y);
-    }
+    for (int k = 0; k < 4; ++k) s = fmaf(w2[k], fmaxf(fmaf(w1[k], u, b1[k]), 0.0f), s);
+    return s;
+}
+
+__device__ __forceinline__ int32_t rmi_offset_from_y(float y, uint32_t cnt) {
     float r = rintf(y * (float)cnt);
     r = fminf(fmaxf(r, 0.0f), (float)cnt);
     return (int32_t)r;
+}
+
+__device__ __forceinline__ float rmi_u(uint32_t dx, float kinv) { return (float)dx * kinv; }
+
+// IEEE binary16 <-> fp32 (round to nearest even) for the stored leaf weights.
+__device__ __forceinline__ float h2f(uint32_t bits) { return (float)__builtin_bit_cast(_Float16, (uint16_t)bits); }
+__device__ __forceinline__ uint32_t f2h(float f) { return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f); }
+
+// Rank offset predicted inside a leaf for a key x with kmin <= x (dx = x - kmin);
+// p holds the stored weights (w1, b1, w2 already rounded to binary16) and b2.
+__device__ __forceinline__ int32_t rmi_pred_offset(const float* p, uint32_t cnt, float kinv, uint32_t dx) {
+    const float u = rmi_u(dx, kinv);
+    const float s0 = rmi_quad_partial(p + 0, p + 16, p + 32, u);
+    const float s1 = rmi_quad_partial(p + 4, p + 20, p + 36, u);
+    const float s2 = rmi_quad_partial(p + 8, p + 24, p + 40, u);
+    const float s3 = rmi_quad_partial(p + 12, p + 28, p + 44, u);
+    const float y = p[48] + ((s0 + s1) + (s2 + s3));
+    return rmi_offset_from_y(y, cnt);
 }
 
 // ------------------------------------------------------------------ host launchers
@@ -124,6 +155,7 @@ struct LaunchCfg {
 };
 
 int device_cu_count();
+size_t device_lds_per_block();
 int resolve_launch(const bits_ref* ref, const bits_launch* in, LaunchCfg* out);
 SearchArgs make_search_args(const bits_ref* ref, const LaunchCfg& cfg);
 
@@ -139,6 +171,8 @@ hipError_t launch_mc(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t*
                      const uint32_t* off, const uint32_t* span, const uint32_t* len, uint64_t na,
                      uint64_t seed, uint64_t s0, uint64_t nshuf, unsigned long long* totals,
                      unsigned long long* observed, hipStream_t s);
+hipError_t launch_rmi_window(const SearchArgs& sa, uint32_t which, const uint32_t* xs, uint64_t n, uint32_t* lo,
+                             uint32_t* hi, hipStream_t s);
 hipError_t launch_mc_tail(const unsigned long long* totals, uint64_t nshuf, const unsigned long long* observed,
                           unsigned long long* n_ge, unsigned long long* n_le, hipStream_t s);
 hipError_t launch_project(const uint32_t* chrom_len, uint32_t n_chrom, const uint32_t* chrom,

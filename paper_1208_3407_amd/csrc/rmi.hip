@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(kTrainWaves * kWave) k_rmi_train(Pair2 P, Trai
     const uint32_t cnt = P.bounds[a][leaf + 1] - rlo;
     uint32_t* Lw = reinterpret_cast<uint32_t*>(L);
     if (cnt == 0) {
-        Lw[lane] = lane == 0 ? 0xFFFFFFFFu : lane == 2 ? rlo : 0u;
+        if (lane < 32) Lw[lane] = lane == 0 ? 0xFFFFFFFFu : lane == 4 ? rlo : 0u;
         return;
     }
     const uint32_t kmin = K[rlo], kmax = K[rlo + cnt - 1];
@@ -293,30 +293,47 @@ __global__ void __launch_bounds__(kTrainWaves * kWave) k_rmi_train(Pair2 P, Trai
     wave_grad(p, u, t, m, g);
     const float last_loss = g[kNP] / (float)m;
 
+    // The stored model: w1, b1, w2 rounded to binary16, b2 kept in fp32.
+    float q[kNP];
+#pragma unroll
+    for (int j = 0; j < 48; ++j) q[j] = h2f(f2h(p[j]));
+    q[48] = p[48];
     // Error window over every key of the leaf (first occurrence of each
     // value; x == kmin is answered without a search), with the query-time
-    // prediction code.
+    // prediction arithmetic on the stored model.
     int32_t over = 0, under = 0;
     for (uint32_t i = rlo + lane; i < rlo + cnt; i += kWave) {
         const uint32_t x = K[i];
         if (x == kmin) continue;
         if (K[i - 1] == x) continue;   // i > rlo here because x > kmin
-        const int32_t e = rmi_pred_offset(p, cnt, kinv, x - kmin) - (int32_t)(i - rlo);
+        const int32_t e = rmi_pred_offset(q, cnt, kinv, x - kmin) - (int32_t)(i - rlo);
         over = max(over, e);
         under = max(under, -e);
     }
-    over = wave_max_i32(over);
-    under = wave_max_i32(under);
-    if (lane < (uint32_t)kNP) L->p[lane] = own;
+    over = min(wave_max_i32(over), 65535);
+    under = min(wave_max_i32(under), 65535);
     if (lane == 0) {
-        L->kmin = kmin;
-        L->kmax = kmax;
-        L->rlo = rlo;
-        L->cnt = cnt;
-        L->kinv = kinv;
-        L->err_lo = over;
-        L->err_hi = under;
-        L->loss = last_loss;
+        uint32_t w[32];
+        w[0] = kmin;
+        w[1] = kmax;
+        w[4] = rlo;
+        w[5] = cnt;
+        w[8] = __float_as_uint(kinv);
+        w[9] = __float_as_uint(q[48]);
+        w[12] = (uint32_t)over | ((uint32_t)under << 16);
+        w[13] = __float_as_uint(last_loss);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            w[4 * g + 2] = f2h(q[4 * g + 0]) | (f2h(q[4 * g + 1]) << 16);          // w1
+            w[4 * g + 3] = f2h(q[4 * g + 2]) | (f2h(q[4 * g + 3]) << 16);
+            w[16 + 4 * g + 0] = f2h(q[16 + 4 * g + 0]) | (f2h(q[16 + 4 * g + 1]) << 16);   // b1
+            w[16 + 4 * g + 1] = f2h(q[16 + 4 * g + 2]) | (f2h(q[16 + 4 * g + 3]) << 16);
+            w[16 + 4 * g + 2] = f2h(q[32 + 4 * g + 0]) | (f2h(q[32 + 4 * g + 1]) << 16);   // w2
+            w[16 + 4 * g + 3] = f2h(q[32 + 4 * g + 2]) | (f2h(q[32 + 4 * g + 3]) << 16);
+        }
+        uint4* dst = reinterpret_cast<uint4*>(L);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) dst[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
     }
 }
 

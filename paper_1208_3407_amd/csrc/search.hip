@@ -16,6 +16,13 @@
 
 #include "bits_internal.hpp"
 
+// Waves per SIMD the search kernels are compiled for (caps their VGPRs).
+#ifndef BITS_SEARCH_WAVES_PER_EU
+#define BITS_SEARCH_WAVES_PER_EU 4
+#endif
+#define BITS_SEARCH_KERNEL __global__ void __launch_bounds__(1024) \
+    __attribute__((amdgpu_waves_per_eu(BITS_SEARCH_WAVES_PER_EU)))
+
 namespace bits {
 
 using u32x4 = uint32_t __attribute__((ext_vector_type(4)));
@@ -49,16 +56,15 @@ __device__ __forceinline__ void bisect_multi(const uint32_t* __restrict__ ks, co
         for (int c = 0; c < NC; ++c) {
             const uint32_t* K = (c & 1) ? ke : ks;
             const uint32_t half = len[c] >> 1;
-            v[c] = 0u;
-            if (half) {
-                // a probe is streamed (non-temporal) unless it is one of the
-                // shared first probes or the range is down to ~2 lines, whose
-                // lines the next probes read again
-                if (step < hot || len[c] <= 64u)
-                    v[c] = ld_key<false>(K + base[c] + half - 1);
-                else
-                    v[c] = ld_key<true>(K + base[c] + half - 1);
-            }
+            // a finished chain reads key 0 (always in bounds); its value is unused.
+            // A probe is streamed (non-temporal) unless it is one of the shared
+            // first probes or the range is down to ~2 lines, which the next
+            // probes read again.
+            const uint32_t idx = half ? base[c] + half - 1 : 0u;
+            if (step < hot || len[c] <= 64u)
+                v[c] = ld_key<false>(K + idx);
+            else
+                v[c] = ld_key<true>(K + idx);
             any |= half != 0;
         }
         if (!any) break;
@@ -85,65 +91,161 @@ __device__ __forceinline__ void bisect_multi(const uint32_t* __restrict__ ks, co
 }
 
 // ------------------------------------------------------------------ line probe
-// For every lane's chains: cnt[c] = #{i in [la[c], lb[c]) : K_c[i] < x[c]},
-// where [la, lb) lies inside one 128-byte line (32 keys; the sorted arrays
-// are 256-byte aligned inside the reference block, which also covers the
-// tail of the last line).  The whole wave cooperates: 8 lanes read one line
-// with 16-byte loads, so one instruction fetches 8 whole lines; the 8 partial
-// counts are summed with lane exchanges.  `scr` is this wave's LDS scratch of
-// 4 * NC * 64 words.  Must be called by all 64 lanes.
+// For every lane's chains with line[c] != kNoLine:
+//   cnt[c] = #{i in [32 line, 32 line + 32) : K_c[i] < x[c]}.
+// Because K_c is sorted, 0 < cnt < 32 pins the global lower bound to
+// 32 line + cnt exactly.  The sorted arrays are 256-byte aligned inside the
+// reference block and the rest of their last 128-byte line holds 0xFFFFFFFF
+// (never < x), so every line read is in bounds and needs no masking.  The
+// whole wave cooperates: kProbeLanes lanes read one line with 16-byte loads
+// (each load instruction covering a contiguous 16 * kProbeLanes bytes of every
+// line it touches) and their partial counts are summed with DPP lane moves.
+// `scr` is this wave's LDS scratch of 4 * NC * 64 words.  Must be called by
+// all 64 lanes.
+constexpr uint32_t kNoLine = 0xFFFFFFFFu;
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ uint32_t count_lt4(u32x4 v, uint32_t x) {
+    return (v.x < x ? 1u : 0u) + (v.y < x ? 1u : 0u) + (v.z < x ? 1u : 0u) + (v.w < x ? 1u : 0u);
+}
+
+#ifndef BITS_PROBE_LANES
+#define BITS_PROBE_LANES 8
+#endif
+constexpr int kProbeLanes = BITS_PROBE_LANES;        // lanes reading one line
+constexpr int kProbeLoads = 8 / kProbeLanes;         // 16-byte loads per lane per line
+constexpr int kProbeGroups = kWave / kProbeLanes;    // lines per instruction
+
+// Sum over each aligned group of kProbeLanes lanes, in every lane of the group.
+__device__ __forceinline__ uint32_t group_sum(uint32_t t) {
+    if constexpr (kProbeLanes >= 2) t += dpp_u32<0xB1>(t);    // quad_perm [1,0,3,2]
+    if constexpr (kProbeLanes >= 4) t += dpp_u32<0x4E>(t);    // quad_perm [2,3,0,1]
+    if constexpr (kProbeLanes >= 8) t += dpp_u32<0x141>(t);   // row_half_mirror
+    return t;
+}
+
 template <int NC>
 __device__ __forceinline__ void probe_lines(const uint32_t* __restrict__ ks, const uint32_t* __restrict__ ke,
-                                            const uint32_t (&la)[NC], const uint32_t (&lb)[NC],
-                                            const uint32_t (&x)[NC], uint32_t (&cnt)[NC], uint32_t* scr) {
+                                            const uint32_t (&line)[NC], const uint32_t (&x)[NC],
+                                            uint32_t (&cnt)[NC], uint32_t* scr) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        scr[(4 * c + 0) * kWave + lane] = la[c];
-        scr[(4 * c + 1) * kWave + lane] = lb[c];
-        scr[(4 * c + 2) * kWave + lane] = x[c];
+        // an idle lane probes line 0 against x = 0 (counts nothing, result unused)
+        const bool on = line[c] != kNoLine;
+        scr[(2 * c + 0) * 2 * kWave + 2 * lane] = on ? line[c] : 0u;
+        scr[(2 * c + 0) * 2 * kWave + 2 * lane + 1] = on ? x[c] : 0u;
     }
     wave_lds_sync();
-    const uint32_t sub = lane & 7u, grp = lane >> 3;
+    const uint32_t sub = lane % kProbeLanes, grp = lane / kProbeLanes;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const uint32_t* K = (c & 1) ? ke : ks;
-        u32x4 v[8];
-        uint32_t a[8], b[8], xx[8];
+        u32x4 v[kProbeLanes][kProbeLoads];
+        uint32_t xx[kProbeLanes];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const uint32_t owner = (uint32_t)j * 8u + grp;
-            a[j] = scr[(4 * c + 0) * kWave + owner];
-            b[j] = scr[(4 * c + 1) * kWave + owner];
-            xx[j] = scr[(4 * c + 2) * kWave + owner];
-            const uint32_t i0 = (a[j] & ~31u) + 4u * sub;
-            v[j] = (a[j] < b[j]) ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(K + i0)) : u32x4{0, 0, 0, 0};
+        for (int j = 0; j < kProbeLanes; ++j) {
+            const uint32_t owner = (uint32_t)j * kProbeGroups + grp;
+            const uint2 lx = *reinterpret_cast<const uint2*>(scr + (2 * c + 0) * 2 * kWave + 2 * owner);
+            xx[j] = lx.y;
+            // load k covers bytes [16 k L, 16 (k + 1) L) of the line (L lanes), contiguous per group
+            const u32x4* P = reinterpret_cast<const u32x4*>(K + lx.x * 32u) + sub;
+#pragma unroll
+            for (int k = 0; k < kProbeLoads; ++k) v[j][k] = __builtin_nontemporal_load(P + k * kProbeLanes);
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const uint32_t owner = (uint32_t)j * 8u + grp;
-            const uint32_t i0 = (a[j] & ~31u) + 4u * sub;
-            uint32_t n = 0;
-            if (a[j] < b[j]) {
-                n += (i0 + 0 >= a[j] && i0 + 0 < b[j] && v[j].x < xx[j]) ? 1u : 0u;
-                n += (i0 + 1 >= a[j] && i0 + 1 < b[j] && v[j].y < xx[j]) ? 1u : 0u;
-                n += (i0 + 2 >= a[j] && i0 + 2 < b[j] && v[j].z < xx[j]) ? 1u : 0u;
-                n += (i0 + 3 >= a[j] && i0 + 3 < b[j] && v[j].w < xx[j]) ? 1u : 0u;
-            }
-            n += __shfl_xor(n, 1);
-            n += __shfl_xor(n, 2);
-            n += __shfl_xor(n, 4);
-            if (sub == 0) scr[(4 * c + 3) * kWave + owner] = n;
+        for (int j = 0; j < kProbeLanes; ++j) {
+            const uint32_t owner = (uint32_t)j * kProbeGroups + grp;
+            uint32_t t = 0;
+#pragma unroll
+            for (int k = 0; k < kProbeLoads; ++k) t += count_lt4(v[j][k], xx[j]);
+            t = group_sum(t);
+            if (sub == 0) scr[(2 * c + 1) * 2 * kWave + owner] = t;
         }
     }
     wave_lds_sync();
 #pragma unroll
-    for (int c = 0; c < NC; ++c) cnt[c] = scr[(4 * c + 3) * kWave + lane];
+    for (int c = 0; c < NC; ++c) cnt[c] = scr[(2 * c + 1) * 2 * kWave + lane];
     wave_lds_sync();
 }
 
-// Words of LDS probe scratch per wave for QPL queries per lane.
-__host__ __device__ constexpr uint32_t probe_scratch_words(int qpl) { return 4u * 2u * (uint32_t)qpl * kWave; }
+// ------------------------------------------------------------------ leaf model
+// Evaluates the leaf of every lane's chains cooperatively, 4 lanes per leaf:
+// in pass p the quad k of the wave serves owner lane 16 p + k.  Lane q of
+// the quad reads 16 bytes at 16 q and 16 bytes at 64 + 16 q of the owner's
+// 128-byte leaf record (each instruction covers 64 contiguous bytes per
+// quad): two header words and the binary16 weights of hidden units
+// 4q..4q+3.  The quad adds its 4 partial sums with two lane-pair moves (the
+// order b2 + ((s0 + s1) + (s2 + s3)) of rmi_pred_offset) and writes, per
+// owner, {kmin, kmax, rlo, cnt, y, err} to LDS.  `scr` is this wave's
+// scratch; chain c uses words [c * kLeafScr, (c + 1) * kLeafScr): 128 words
+// of (leaf, x) pairs, then 6 result words per owner.  Must be called by all
+// 64 lanes.
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_quad(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+template <int NC>
+__device__ __forceinline__ void quad_leaves(const bits_rmi_model* __restrict__ rmi, const uint32_t (&leaf)[NC],
+                                            const uint32_t (&x)[NC], uint32_t* scr) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        scr[c * kLeafScr + 2 * lane] = leaf[c];
+        scr[c * kLeafScr + 2 * lane + 1] = x[c];
+    }
+    wave_lds_sync();
+    const uint32_t quad = lane >> 2, q = lane & 3u;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const bits_rmi_model* M = rmi + (c & 1);
+        uint4 A[4], B[4];
+        uint32_t xo[4];
+#pragma unroll
+        for (int pass = 0; pass < 4; ++pass) {
+            const uint32_t owner = (uint32_t)pass * 16u + quad;
+            const uint2 lx = *reinterpret_cast<const uint2*>(scr + c * kLeafScr + 2 * owner);
+            xo[pass] = lx.y;
+            const uint4* rec = reinterpret_cast<const uint4*>(M->leaf + lx.x);
+            A[pass] = rec[q];
+            B[pass] = rec[4 + q];
+        }
+#pragma unroll
+        for (int pass = 0; pass < 4; ++pass) {
+            const uint32_t owner = (uint32_t)pass * 16u + quad;
+            // kmin from quad lane 0, kinv from quad lane 2 (lane exchanges: a quad_perm
+            // broadcast DPP folded into the using instruction gave wrong values here)
+            const uint32_t kmin = (uint32_t)__shfl((int)A[pass].x, (int)(lane & ~3u));
+            const uint32_t kinvb = (uint32_t)__shfl((int)A[pass].x, (int)((lane & ~3u) + 2u));
+            const float u = rmi_u(xo[pass] - kmin, __uint_as_float(kinvb));
+            const float w1[4] = {h2f(A[pass].z & 0xFFFFu), h2f(A[pass].z >> 16), h2f(A[pass].w & 0xFFFFu),
+                                 h2f(A[pass].w >> 16)};
+            const float b1[4] = {h2f(B[pass].x & 0xFFFFu), h2f(B[pass].x >> 16), h2f(B[pass].y & 0xFFFFu),
+                                 h2f(B[pass].y >> 16)};
+            const float w2[4] = {h2f(B[pass].z & 0xFFFFu), h2f(B[pass].z >> 16), h2f(B[pass].w & 0xFFFFu),
+                                 h2f(B[pass].w >> 16)};
+            float t = rmi_quad_partial(w1, b1, w2, u);
+            t += __uint_as_float(dpp_quad<0xB1>(__float_as_uint(t)));   // s0+s1, s2+s3
+            t += __uint_as_float(dpp_quad<0x4E>(__float_as_uint(t)));   // (s0+s1)+(s2+s3)
+            // lane 0: {kmin, kmax}; 1: {rlo, cnt}; 2: y = b2 + sum; 3: err
+            uint32_t* res = scr + c * kLeafScr + 2 * kWave + 6 * owner;
+            if (q < 2)
+                *reinterpret_cast<uint2*>(res + 2 * q) = make_uint2(A[pass].x, A[pass].y);
+            else if (q == 2)
+                res[4] = __float_as_uint(__uint_as_float(A[pass].y) + t);
+            else
+                res[5] = A[pass].x;
+        }
+    }
+    wave_lds_sync();
+}
+
 
 // ------------------------------------------------------------------ ICount
 // first = #{B_S <= a.end} = #{B_S < a.end + 1}; last = #{B_E < a.start};
@@ -196,69 +298,100 @@ __device__ __forceinline__ void icount_plain(const SearchArgs& sa, const uint32_
 }
 
 // Learned path.  Must be called by all 64 lanes of the wave (line probe).
+// Leaf stage of the learned path for NC chains (even chains search B_S,
+// odd ones B_E): route, evaluate the leaf model, and set either the resolved
+// rank (base, win = false: x <= kmin or x > kmax) or the error window
+// [wl, wr] and the probe line.  Must be called by all 64 lanes.
+template <int NC>
+__device__ __forceinline__ void learned_windows(const SearchArgs& sa, uint32_t* scr, const uint32_t (&x)[NC],
+                                                uint32_t (&base)[NC], uint32_t (&len)[NC], uint32_t (&wl)[NC],
+                                                uint32_t (&wr)[NC], uint32_t (&rlo)[NC], uint32_t (&rhi)[NC],
+                                                uint32_t (&ln)[NC], bool (&win)[NC]) {
+    uint32_t leaf[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const bits_rmi_model* M = sa.rmi + (c & 1);
+        leaf[c] = rmi_route(M->root_a, M->root_b, x[c]);
+    }
+    quad_leaves<NC>(sa.rmi, leaf, x, scr);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const uint32_t* res = scr + c * kLeafScr + 2 * kWave + 6 * lane;
+        const uint2 ra = *reinterpret_cast<const uint2*>(res), rb = *reinterpret_cast<const uint2*>(res + 2),
+                    rc = *reinterpret_cast<const uint2*>(res + 4);
+        const uint4 r0 = make_uint4(ra.x, ra.y, rb.x, rb.y);   // kmin kmax rlo cnt
+        const uint4 r1 = make_uint4(rc.x, 0u, rc.y, 0u);       // y - err -
+        rlo[c] = r0.z;
+        rhi[c] = r0.z + r0.w;
+        win[c] = false;
+        base[c] = rlo[c];
+        len[c] = 0;
+        ln[c] = kNoLine;
+        wl[c] = wr[c] = 0;
+        if (x[c] > r0.y) {
+            base[c] = rhi[c];
+        } else if (x[c] > r0.x) {
+            win[c] = true;
+            const int32_t pred = (int32_t)r0.z + rmi_offset_from_y(__uint_as_float(r1.x), r0.w);
+            const int32_t lo = pred - (int32_t)(r1.z & 0xFFFFu), hi = pred + (int32_t)(r1.z >> 16);
+            wl[c] = (uint32_t)max(lo, (int32_t)rlo[c]);
+            wr[c] = (uint32_t)min(hi, (int32_t)rhi[c]);
+            if (wr[c] < wl[c]) wr[c] = wl[c];
+            base[c] = wl[c];
+            if (wr[c] > wl[c]) ln[c] = min(max((uint32_t)max(pred, 0), wl[c]), wr[c] - 1u) >> 5;
+        }
+    }
+}
+
 template <int QPL>
 __device__ __forceinline__ void icount_learned(const SearchArgs& sa, uint32_t* scr, const uint32_t (&as)[QPL],
                                                const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL]) {
     constexpr int NC = 2 * QPL;
-    uint32_t x[NC], base[NC], len[NC], wl[NC], wr[NC], rlo[NC], rhi[NC], pa[NC], pb[NC], pc[NC];
+    uint32_t x[NC], base[NC], len[NC], wl[NC], wr[NC], rlo[NC], rhi[NC], ln[NC], pc[NC];
     bool win[NC];
 #pragma unroll
     for (int q = 0; q < QPL; ++q) {
         x[2 * q] = ae[q] + 1u;
         x[2 * q + 1] = as[q];
     }
+    learned_windows<NC>(sa, scr, x, base, len, wl, wr, rlo, rhi, ln, win);
+    probe_lines<NC>(sa.bs, sa.be, ln, x, pc, scr);
+    bool exact[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        const bits_rmi_model* M = sa.rmi + (c & 1);
-        const uint32_t leaf = rmi_route(M->root_a, M->root_b, x[c]);
-        const bits_rmi_leaf* L = M->leaf + leaf;
-        const uint4 h0 = *reinterpret_cast<const uint4*>(L);                       // kmin kmax rlo cnt
-        const uint4 h1 = *reinterpret_cast<const uint4*>(&L->kinv);                // kinv err_lo err_hi loss
-        rlo[c] = h0.z;
-        rhi[c] = h0.z + h0.w;
-        win[c] = false;
-        base[c] = rlo[c];
-        len[c] = 0;
-        pa[c] = pb[c] = 0;
-        wl[c] = wr[c] = 0;
-        if (x[c] > h0.y) {
-            base[c] = rhi[c];
-        } else if (x[c] > h0.x) {
-            const int32_t off = rmi_pred_offset(L->p, h0.w, __uint_as_float(h1.x), x[c] - h0.x);
-            const int32_t pred = (int32_t)h0.z + off;
-            const int32_t lo = pred - (int32_t)h1.y, hi = pred + (int32_t)h1.z;
-            wl[c] = (uint32_t)max(lo, (int32_t)rlo[c]);
-            wr[c] = (uint32_t)min(hi, (int32_t)rhi[c]);
-            if (wr[c] < wl[c]) wr[c] = wl[c];
-            base[c] = wl[c];
-            win[c] = true;
-            if (wr[c] > wl[c]) {
-                const uint32_t p = min(max((uint32_t)max(pred, 0), wl[c]), wr[c] - 1u);
-                const uint32_t line = p & ~31u;
-                pa[c] = max(line, wl[c]);
-                pb[c] = min(line + 32u, wr[c]);
-            }
-        }
-    }
-    probe_lines<NC>(sa.bs, sa.be, pa, pb, x, pc, scr);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        if (!win[c] || pb[c] == pa[c]) continue;
-        if (pc[c] > 0 && pc[c] < pb[c] - pa[c]) {
-            base[c] = pa[c] + pc[c];
+        exact[c] = false;
+        if (ln[c] == kNoLine) continue;
+        const uint32_t l0 = ln[c] * 32u, l1 = min(l0 + 32u, sa.n);
+        if ((pc[c] == 0 && l0 < rlo[c]) || (pc[c] >= l1 - l0 && l1 > rhi[c])) {
+            // impossible for a consistent index (the lower bound lies in
+            // [rlo, rhi]); bisect the leaf's whole range instead
+            wl[c] = rlo[c];
+            wr[c] = rhi[c];
+            base[c] = rlo[c];
+            len[c] = rhi[c] - rlo[c];
+        } else if (pc[c] > 0 && l0 + pc[c] < l1) {
+            base[c] = l0 + pc[c];        // the global lower bound: K[l0+pc-1] < x <= K[l0+pc]
+            exact[c] = true;
         } else if (pc[c] == 0) {
+            // lower bound <= l0 (K[l0] >= x); the line may start left of the
+            // window, which then widens to it (l0 >= rlo holds here because
+            // the lower bound is >= rlo)
+            wl[c] = min(wl[c], l0);
             base[c] = wl[c];
-            len[c] = pa[c] - wl[c];
+            len[c] = l0 - wl[c];
         } else {
-            base[c] = pb[c];
-            len[c] = wr[c] - pb[c];
+            // lower bound >= l1 (every key of the line < x); symmetric
+            wr[c] = max(wr[c], l1);
+            base[c] = l1;
+            len[c] = wr[c] - l1;
         }
     }
     bisect_multi<NC>(sa.bs, sa.be, base, len, x, 0u);
     bool any_fb = false;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        if (!win[c]) continue;
+        if (!win[c] || exact[c]) continue;
         const uint32_t* K = (c & 1) ? sa.be : sa.bs;
         const uint32_t r = base[c];
         bool ok = true;
@@ -288,11 +421,6 @@ __device__ __forceinline__ void icount(const SearchArgs& sa, uint32_t* lds, cons
         icount_plain<QPL>(sa, lds, as, ae, cnt);
 }
 
-// Dynamic LDS of a search kernel: the top trees (plain) or the per-wave probe
-// scratch (learned).
-__host__ __device__ constexpr size_t search_lds_bytes(bool learned, uint32_t depth, int qpl, uint32_t block) {
-    return learned ? (size_t)(block / kWave) * probe_scratch_words(qpl) * 4u : (size_t)tree_lds_words(depth) * 4u;
-}
 
 // ------------------------------------------------------------------ counting kernel
 // Persistent grid over tiles of blockDim*QPL queries; query i of a tile is
@@ -300,7 +428,7 @@ __host__ __device__ constexpr size_t search_lds_bytes(bool learned, uint32_t dep
 // coalesced.  Totals: uint64 wave sum, one atomic per wave.
 
 template <int QPL, bool LEARNED>
-__global__ void __launch_bounds__(1024) k_count(SearchArgs sa, const uint32_t* __restrict__ a_start,
+BITS_SEARCH_KERNEL k_count(SearchArgs sa, const uint32_t* __restrict__ a_start,
                                                 const uint32_t* __restrict__ a_end, uint64_t na,
                                                 uint32_t* __restrict__ counts, unsigned long long* total) {
     extern __shared__ uint32_t lds[];
@@ -355,8 +483,7 @@ __global__ void __launch_bounds__(1024) k_count(SearchArgs sa, const uint32_t* _
 constexpr uint32_t kMaxChunk = 64;
 
 template <int QPL, bool LEARNED, bool OBSERVED>
-__global__ void __launch_bounds__(1024)
-    k_mc(SearchArgs sa, const uint32_t* __restrict__ a_start, const uint32_t* __restrict__ a_end,
+BITS_SEARCH_KERNEL k_mc(SearchArgs sa, const uint32_t* __restrict__ a_start, const uint32_t* __restrict__ a_end,
          const uint32_t* __restrict__ off, const uint32_t* __restrict__ span, const uint32_t* __restrict__ len,
          uint64_t na, uint64_t seed, uint64_t s0, uint64_t nshuf, uint64_t tiles, uint32_t chunk,
          unsigned long long* __restrict__ totals) {
@@ -568,6 +695,37 @@ __global__ void __launch_bounds__(1024)
     if (bad) atomicOr(status, BITS_FLAG_INTERVAL);
 }
 
+// ------------------------------------------------------------------ window hook
+// For keys x[i]: the learned path's window for array `which` (0 = B_S,
+// 1 = B_E): lo = wl, hi = wr, or lo = hi = the resolved rank.
+__global__ void __launch_bounds__(256) k_rmi_window(SearchArgs sa, uint32_t which, const uint32_t* __restrict__ xs,
+                                                    uint64_t n, uint32_t* __restrict__ lo, uint32_t* __restrict__ hi) {
+    extern __shared__ uint32_t lds[];
+    uint32_t* scr = lds + (threadIdx.x / kWave) * probe_scratch_words(1);
+    const uint64_t tiles = (n + blockDim.x - 1) / blockDim.x;
+    for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint64_t i = t * blockDim.x + threadIdx.x;
+        const uint32_t xi = i < n ? xs[i] : 0u;
+        uint32_t x[2] = {xi, xi}, base[2], len[2], wl[2], wr[2], rlo[2], rhi[2], ln[2];
+        bool win[2];
+        learned_windows<2>(sa, scr, x, base, len, wl, wr, rlo, rhi, ln, win);
+        if (i < n) {
+            lo[i] = win[which] ? wl[which] : base[which];
+            hi[i] = win[which] ? wr[which] : base[which];
+        }
+    }
+}
+
+hipError_t launch_rmi_window(const SearchArgs& sa, uint32_t which, const uint32_t* xs, uint64_t n, uint32_t* lo,
+                             uint32_t* hi, hipStream_t s) {
+    if (!n) return hipSuccess;
+    uint64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_rmi_window, dim3((uint32_t)g), dim3(256), search_lds_bytes(true, 0, 1, 256), s, sa, which,
+                       xs, n, lo, hi);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ fills
 __global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
@@ -588,6 +746,19 @@ int device_cu_count() {
         int cu = 0;
         if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
         cached[dev] = cu;
+    }
+    return cached[dev];
+}
+
+size_t device_lds_per_block() {
+    static size_t cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+    if (!cached[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 65536;
+        cached[dev] = (size_t)v;
     }
     return cached[dev];
 }

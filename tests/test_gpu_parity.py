@@ -260,18 +260,41 @@ def test_learned_index_metadata():
     raw = down(ref.rmi_bytes())
     for a, keys in enumerate((np.sort(ob_s), np.sort(ob_e))):
         base = a * bits.RMI_MODEL_BYTES
-        hdr = raw[base:base + 256]
+        hdr = raw[base:base + bits.RMI_HEADER_BYTES]
         fit_a, fit_b = np.frombuffer(hdr[8:24].tobytes(), np.float64)
         oa, ob = oracle.linear_fit(keys)
         assert abs(fit_a - oa) <= 1e-9 * abs(oa) and abs(fit_b - ob) <= 1e-6 * max(1.0, abs(ob))
-        leaves = raw[base + 256: base + bits.RMI_MODEL_BYTES].reshape(4096, 256)
-        u32 = leaves[:, :16].copy().view(np.uint32)
-        rlo, cnt = u32[:, 2].astype(np.int64), u32[:, 3].astype(np.int64)
+        leaves = raw[base + bits.RMI_HEADER_BYTES: base + bits.RMI_MODEL_BYTES].reshape(4096, 128)
+        u32 = leaves.copy().view(np.uint32)          # 32 words per leaf
+        kmin, kmax, rlo, cnt = u32[:, 0], u32[:, 1], u32[:, 4].astype(np.int64), u32[:, 5].astype(np.int64)
         # leaves tile the rank range in order
         assert rlo[0] == 0 and rlo[-1] + cnt[-1] == len(keys)
         assert np.all(rlo[1:] == rlo[:-1] + cnt[:-1])
         nz = cnt > 0
-        assert np.array_equal(u32[nz, 0], keys[rlo[nz]])
-        assert np.array_equal(u32[nz, 1], keys[rlo[nz] + cnt[nz] - 1])
+        assert np.array_equal(kmin[nz], keys[rlo[nz]])
+        assert np.array_equal(kmax[nz], keys[rlo[nz] + cnt[nz] - 1])
+        assert np.all(kmin[~nz] == 0xFFFFFFFF)
+        # kinv = 1 / max(1, kmax - kmin) in fp32
+        kinv = u32[nz, 8].view(np.float32)
+        span = np.maximum(kmax[nz].astype(np.int64) - kmin[nz], 1).astype(np.float32)
+        assert np.array_equal(kinv, (np.float32(1.0) / span).astype(np.float32))
     info = bits.bits_rmi_info(ref)
     assert info["mean_window"] >= 1 and info["max_window"] >= 1
+
+
+def test_learned_windows_hold_every_key():
+    """The query path's window (bits_rmi_window runs the searches' own device
+    code) must contain the lower-bound rank of every key of the array: this
+    is what the per-leaf error windows promise, independently of the
+    verification that keeps the searches exact."""
+    note("case: learned windows")
+    for seed, nb in ((4, 300_000), (5, 70_001)):
+        lengths, _, B = datagen.w1_sets(seed=seed, n_a=1, n_b=nb)
+        b_s, b_e, ob_s, ob_e = project_both(lengths, B)
+        ref = bits.bits_sort_ref(b_s, b_e, learned=True, train={"epochs": 50})
+        for which, keys in ((0, np.sort(ob_s)), (1, np.sort(ob_e))):
+            lo, hi = bits.bits_rmi_window(ref, which, up(keys))
+            lo, hi = down(lo).astype(np.int64), down(hi).astype(np.int64)
+            rank = np.searchsorted(keys, keys, side="left")
+            bad = np.flatnonzero((rank < lo) | (rank > hi))
+            assert bad.size == 0, (which, bad[:5], rank[bad[:5]], lo[bad[:5]], hi[bad[:5]])
