@@ -82,6 +82,9 @@ typedef struct bits_launch {
  *   tree         uint32[2][2^depth]: Eytzinger splitters of B_S then B_E,
  *                node k (1-based BFS order) at [k]; entry 0 unused
  *   rmi          (learned only) 2 x bits_rmi_model (128-byte header + 4096 leaves)
+ *   heads        (learned only) uint32[2][hl], line heads of B_S then B_E:
+ *                H[j] = K[32 j] (first key of each 128-byte line) for j < ceil(n/32),
+ *                then 0xFFFFFFFF; hl = 32 * ceil((ceil(n/32) + 32) / 32)
  *   bs, be       uint32[n] each: sorted B_S and B_E (Sec. 2.1, Algorithm 2); the rest
  *                of each array's last 128-byte line is filled with 0xFFFFFFFF */
 typedef struct bits_ref {
@@ -92,6 +95,7 @@ typedef struct bits_ref {
     uint32_t *be;        /* device: sorted ends */
     uint32_t *tree;      /* device: 2 * 2^depth splitters */
     void *rmi;           /* device: 2 bits_rmi_model (starts, ends) or NULL */
+    uint32_t *heads;     /* device: line heads of B_S, then of B_E (learned only) or NULL */
     uint32_t *status;    /* device: status word and counters */
     void *block;         /* device: base of the caller's block */
     size_t block_bytes;
@@ -128,7 +132,7 @@ typedef struct bits_rmi_model {
 /* Training settings for the learned index (NULL = defaults). */
 typedef struct bits_train {
     uint32_t epochs;      /* full-batch Adam steps per leaf (default 300; 0 = init only) */
-    uint32_t max_points;  /* training points per leaf, stride-sampled (default 256, max 2048) */
+    uint32_t max_points;  /* training points per leaf, stride-sampled (0 = default 256; above 2048 clamps to 2048) */
     float lr;             /* Adam step size (default 2e-3) */
     float beta1, beta2;   /* Adam moments (defaults 0.9, 0.999) */
 } bits_train;
@@ -239,7 +243,8 @@ int bits_count(const bits_ref *ref, const uint32_t *d_a_start, const uint32_t *d
 /* Monte-Carlo significance (Sec. 3.2)                                      */
 /* ---------------------------------------------------------------------- */
 
-/* Workspace bytes bits_mc_pvalue needs for na queries. */
+/* Workspace bytes bits_mc_pvalue needs for na queries (na < 2^32):
+ * a per-query table of 16 bytes plus 2 KiB. */
 int bits_mc_workspace(uint64_t na, size_t *bytes);
 
 /* Shuffles the query set A against the fixed reference and counts, in one
@@ -256,7 +261,11 @@ int bits_mc_workspace(uint64_t na, size_t *bytes);
  *   d_observed       device uint64: total of the unshuffled A
  *   d_n_ge, d_n_le   device uint64: #{s : T_s >= T_obs}, #{s : T_s <= T_obs}
  * The one-sided empirical p-value is bits_pvalue(n_ge, s1 - s0).  A query
- * outside its chromosome sets BITS_FLAG_CHROM and is left out of every total. */
+ * outside its chromosome sets BITS_FLAG_CHROM and is left out of every total.
+ * The queries are first grouped by chromosome in d_ws, and the shuffles run
+ * over that table with one group of workgroups per part of the genome; with
+ * the learned path, each search is the leaf model, one window of line heads
+ * and one line of the sorted array.  na must be < 2^32 (BITS_E_ARG). */
 int bits_mc_pvalue(const bits_ref *ref, const uint32_t *d_a_start, const uint32_t *d_a_end,
                    uint64_t na, const uint32_t *chrom_len, uint32_t n_chrom, uint64_t seed,
                    uint64_t s0, uint64_t s1, void *d_ws, size_t ws_bytes, uint64_t *d_totals,

@@ -39,7 +39,7 @@ class bits_launch(ctypes.Structure):
 
 class bits_ref(ctypes.Structure):
     _fields_ = [("n", _u64), ("depth", _u32), ("learned", _u32), ("bs", _vp), ("be", _vp), ("tree", _vp),
-                ("rmi", _vp), ("status", _vp), ("block", _vp), ("block_bytes", _sz)]
+                ("rmi", _vp), ("heads", _vp), ("status", _vp), ("block", _vp), ("block_bytes", _sz)]
 
 
 class bits_train(ctypes.Structure):
@@ -219,6 +219,16 @@ class Ref:
 
     def tree(self) -> torch.Tensor:
         return self._view(self.c.tree, 2 << self.depth, torch.uint32)
+
+    def heads_len(self) -> int:
+        """Entries of one line-head array (learned references)."""
+        return ((self.n + 31) // 32 + 32 + 31) // 32 * 32
+
+    def heads(self) -> torch.Tensor:
+        """Line heads [2, heads_len]: first key of every 128-byte line of B_S, B_E."""
+        if not self.learned:
+            raise BitsError("the reference has no learned index")
+        return self._view(self.c.heads, 2 * self.heads_len(), torch.uint32).view(2, -1)
 
     def rmi_bytes(self) -> torch.Tensor:
         if not self.learned:

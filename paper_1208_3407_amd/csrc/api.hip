@@ -29,7 +29,7 @@ uint32_t clamp_depth(uint64_t n, uint32_t depth) {
 }
 
 struct RefLayout {
-    size_t status, tree, rmi, bs, be, total;
+    size_t status, tree, rmi, heads, bs, be, total;
 };
 
 RefLayout ref_layout(uint64_t n, uint32_t depth, int learned) {
@@ -38,6 +38,7 @@ RefLayout ref_layout(uint64_t n, uint32_t depth, int learned) {
     L.status = o; o = align256(o + kStatusBytes);
     L.tree = o; o = align256(o + (size_t)2 * ((size_t)1 << depth) * sizeof(uint32_t));
     L.rmi = o; o = align256(o + (learned ? 2 * sizeof(bits_rmi_model) : 0));
+    L.heads = o; o = align256(o + (learned ? 2 * heads_len(n) * sizeof(uint32_t) : 0));
     L.bs = o; o = align256(o + (size_t)n * sizeof(uint32_t));
     L.be = o; o = align256(o + (size_t)n * sizeof(uint32_t));
     L.total = o;
@@ -47,7 +48,7 @@ RefLayout ref_layout(uint64_t n, uint32_t depth, int learned) {
 bool ref_ok(const bits_ref* r) {
     if (!r || !r->status || !r->tree || r->n > 0xFFFFFFFFull) return false;
     if (r->n && (!r->bs || !r->be)) return false;
-    if (r->learned && !r->rmi) return false;
+    if (r->learned && (!r->rmi || !r->heads)) return false;
     return r->depth <= BITS_MAX_DEPTH;
 }
 
@@ -55,7 +56,8 @@ bits_train train_defaults(const bits_train* t) {
     bits_train d{300u, 256u, 2e-3f, 0.9f, 0.999f};
     if (!t) return d;
     bits_train r = *t;
-    if (r.max_points == 0 || r.max_points > BITS_RMI_MAX_POINTS) r.max_points = BITS_RMI_MAX_POINTS;
+    if (r.max_points == 0) r.max_points = d.max_points;
+    if (r.max_points > BITS_RMI_MAX_POINTS) r.max_points = BITS_RMI_MAX_POINTS;
     if (!(r.lr > 0.0f)) r.lr = d.lr;
     if (!(r.beta1 > 0.0f && r.beta1 < 1.0f)) r.beta1 = d.beta1;
     if (!(r.beta2 > 0.0f && r.beta2 < 1.0f)) r.beta2 = d.beta2;
@@ -100,6 +102,8 @@ SearchArgs make_search_args(const bits_ref* ref, const LaunchCfg& cfg) {
     sa.be = ref->be;
     sa.tree = ref->tree;
     sa.rmi = (const bits_rmi_model*)ref->rmi;
+    sa.hs = ref->heads;
+    sa.he = ref->heads ? ref->heads + heads_len(ref->n) : nullptr;
     sa.status = ref->status;
     sa.fallbacks = fallback_counter(ref);
     sa.n = (uint32_t)ref->n;
@@ -180,6 +184,7 @@ int bits_ref_init(void* d_block, size_t block_bytes, uint64_t n, uint32_t depth,
     ref->status = (uint32_t*)(b + L.status);
     ref->tree = (uint32_t*)(b + L.tree);
     ref->rmi = learned ? (void*)(b + L.rmi) : nullptr;
+    ref->heads = learned ? (uint32_t*)(b + L.heads) : nullptr;
     ref->bs = (uint32_t*)(b + L.bs);
     ref->be = (uint32_t*)(b + L.be);
     ref->block = d_block;
@@ -218,6 +223,8 @@ static int finish_ref(const bits_ref* r, const bits_train& tr, void* ws, hipStre
         BITS_CHECK_HIP(launch_fill_u32(r->tree, (uint64_t)2 << r->depth, 0u, s));
     }
     if (r->learned) {
+        BITS_CHECK_HIP(launch_build_heads(r->bs, r->n, r->heads, s));
+        BITS_CHECK_HIP(launch_build_heads(r->be, r->n, r->heads + heads_len(r->n), s));
         bits_rmi_model* m = (bits_rmi_model*)r->rmi;
         if (r->n == 0) {
             BITS_CHECK_HIP(launch_fill_u32((uint32_t*)m, 2 * sizeof(bits_rmi_model) / 4, 0u, s));
@@ -350,8 +357,8 @@ int bits_count(const bits_ref* ref, const uint32_t* d_a_start, const uint32_t* d
 }
 
 int bits_mc_workspace(uint64_t na, size_t* bytes) {
-    if (!bytes) return BITS_E_ARG;
-    *bytes = 3 * align256((size_t)na * sizeof(uint32_t));
+    if (!bytes || na > 0xFFFFFFFFull) return BITS_E_ARG;
+    *bytes = 4 * align256((size_t)na * sizeof(uint32_t)) + 2 * align256(BITS_MAX_CHROM * sizeof(uint32_t));
     return BITS_OK;
 }
 
@@ -364,6 +371,7 @@ int bits_mc_pvalue(const bits_ref* ref, const uint32_t* d_a_start, const uint32_
     if (s1 < s0 || !chrom_len || n_chrom == 0 || n_chrom > BITS_MAX_CHROM) return BITS_E_ARG;
     if (!d_observed || !d_n_ge || !d_n_le || (s1 > s0 && !d_totals)) return BITS_E_ARG;
     const uint64_t ns = s1 - s0;
+    if (na > 0xFFFFFFFFull) return BITS_E_ARG;
     if (na && ns > ~0ull / na) return BITS_E_ARG;   // counter g = s * na + i must not wrap
     if (na && s1 > (~0ull - na) / na) return BITS_E_ARG;
     uint64_t g = 0;
@@ -382,12 +390,18 @@ int bits_mc_pvalue(const bits_ref* ref, const uint32_t* d_a_start, const uint32_
     BITS_CHECK_HIP(launch_fill_u64(obs, 1, 0ull, s));
     if (na && ref->n) {
         const size_t stride = align256((size_t)na * sizeof(uint32_t));
-        uint32_t* off = (uint32_t*)d_ws;
-        uint32_t* span = (uint32_t*)((char*)d_ws + stride);
-        uint32_t* len = (uint32_t*)((char*)d_ws + 2 * stride);
-        BITS_CHECK_HIP(launch_mc_prepare(d_a_start, d_a_end, na, chrom_len, n_chrom, off, span, len, ref->status, s));
-        BITS_CHECK_HIP(launch_mc(make_search_args(ref, cfg), cfg, d_a_start, d_a_end, off, span, len, na, seed, s0,
-                                 ns, totals, obs, s));
+        const size_t cstride = align256(BITS_MAX_CHROM * sizeof(uint32_t));
+        char* w = (char*)d_ws;
+        McTable tab;
+        tab.off = (uint32_t*)w;
+        tab.span = (uint32_t*)(w + stride);
+        tab.len = (uint32_t*)(w + 2 * stride);
+        tab.idx = (uint32_t*)(w + 3 * stride);
+        tab.hist = (uint32_t*)(w + 4 * stride);
+        tab.cursor = (uint32_t*)(w + 4 * stride + cstride);
+        BITS_CHECK_HIP(launch_mc_prepare(d_a_start, d_a_end, na, chrom_len, n_chrom, tab, ref->status, s));
+        BITS_CHECK_HIP(launch_mc(make_search_args(ref, cfg), cfg, d_a_start, d_a_end, tab, na, seed, s0, ns, totals,
+                                 obs, s));
     }
     BITS_CHECK_HIP(launch_mc_tail(totals, ns, obs, (unsigned long long*)d_n_ge, (unsigned long long*)d_n_le, s));
     return BITS_OK;

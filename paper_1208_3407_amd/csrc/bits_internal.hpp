@@ -72,12 +72,19 @@ struct SearchArgs {
     const uint32_t* be;          // sorted ends
     const uint32_t* tree;        // [2][tree_stride] Eytzinger splitters
     const bits_rmi_model* rmi;   // [2] learned models or nullptr
+    const uint32_t* hs;          // line heads of B_S (learned only): hs[j] = bs[32 j], 0xFFFFFFFF past the end
+    const uint32_t* he;          // line heads of B_E
     uint32_t* status;            // device status word
     unsigned long long* fallbacks;
     uint32_t n;                  // |B|
     uint32_t tree_stride;        // 2^built_depth
     uint32_t depth;              // levels searched from LDS (<= built depth)
 };
+
+// Entries of one line-head array for n keys: ceil(n / 32) heads plus at
+// least 32 entries of 0xFFFFFFFF, rounded up to whole 128-byte lines, so a
+// 32-entry window starting at or before head ceil(n / 32) - 1 + 16 stays in bounds.
+__host__ __device__ constexpr uint64_t heads_len(uint64_t n) { return ((n + 31) / 32 + 32 + 31) / 32 * 32; }
 
 // Number of LDS words a search kernel stages for depth d (both arrays).
 __host__ __device__ constexpr uint32_t tree_lds_words(uint32_t d) { return d ? (2u << d) : 0u; }
@@ -164,13 +171,17 @@ hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_count(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
                         uint64_t na, uint32_t* counts, unsigned long long* total, hipStream_t s);
+// Monte-Carlo query table in the caller's workspace: uint32[na] each of
+// chromosome offset, legal-start count, length and original index, grouped
+// by chromosome; hist and cursor hold BITS_MAX_CHROM words each.
+struct McTable {
+    uint32_t *off, *span, *len, *idx, *hist, *cursor;
+};
 hipError_t launch_mc_prepare(const uint32_t* as, const uint32_t* ae, uint64_t na, const uint32_t* chrom_len,
-                             uint32_t n_chrom, uint32_t* off, uint32_t* span, uint32_t* len, uint32_t* status,
-                             hipStream_t s);
+                             uint32_t n_chrom, const McTable& tab, uint32_t* status, hipStream_t s);
 hipError_t launch_mc(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
-                     const uint32_t* off, const uint32_t* span, const uint32_t* len, uint64_t na,
-                     uint64_t seed, uint64_t s0, uint64_t nshuf, unsigned long long* totals,
-                     unsigned long long* observed, hipStream_t s);
+                     const McTable& tab, uint64_t na, uint64_t seed, uint64_t s0, uint64_t nshuf,
+                     unsigned long long* totals, unsigned long long* observed, hipStream_t s);
 hipError_t launch_rmi_window(const SearchArgs& sa, uint32_t which, const uint32_t* xs, uint64_t n, uint32_t* lo,
                              uint32_t* hi, hipStream_t s);
 hipError_t launch_mc_tail(const unsigned long long* totals, uint64_t nshuf, const unsigned long long* observed,
@@ -208,6 +219,9 @@ struct SortSeg {
 size_t sort_workspace_bytes(const uint64_t* n, uint32_t nseg);
 int launch_sort(const SortSeg* segs, uint32_t nseg, void* ws, size_t ws_bytes, hipStream_t s);
 hipError_t launch_build_tree(const uint32_t* keys, uint64_t n, uint32_t depth, uint32_t* tree, hipStream_t s);
+// Line heads of a sorted array: H[j] = keys[32 j] for j < ceil(n / 32), then
+// 0xFFFFFFFF up to heads_len(n) entries.
+hipError_t launch_build_heads(const uint32_t* keys, uint64_t n, uint32_t* heads, hipStream_t s);
 
 // rmi.hip
 size_t rmi_workspace_bytes();

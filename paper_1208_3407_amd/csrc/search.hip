@@ -91,17 +91,20 @@ __device__ __forceinline__ void bisect_multi(const uint32_t* __restrict__ ks, co
 }
 
 // ------------------------------------------------------------------ line probe
-// For every lane's chains with line[c] != kNoLine:
-//   cnt[c] = #{i in [32 line, 32 line + 32) : K_c[i] < x[c]}.
-// Because K_c is sorted, 0 < cnt < 32 pins the global lower bound to
-// 32 line + cnt exactly.  The sorted arrays are 256-byte aligned inside the
+// For every lane's chains with start[c] != kNoLine:
+//   cnt[c] = #{i in [start[c], start[c] + 32) : K_c[i] < x[c]},
+// start a multiple of 4 (16-byte aligned).  On a sorted array probed at a
+// 128-byte line (start = 32 line), 0 < cnt < 32 pins the global lower bound
+// to start + cnt exactly.  The sorted arrays are 256-byte aligned inside the
 // reference block and the rest of their last 128-byte line holds 0xFFFFFFFF
-// (never < x), so every line read is in bounds and needs no masking.  The
-// whole wave cooperates: kProbeLanes lanes read one line with 16-byte loads
-// (each load instruction covering a contiguous 16 * kProbeLanes bytes of every
-// line it touches) and their partial counts are summed with DPP lane moves.
-// `scr` is this wave's LDS scratch of 4 * NC * 64 words.  Must be called by
-// all 64 lanes.
+// (never < x), so every line read is in bounds and needs no masking; the
+// line-head arrays are padded the same way.  The whole wave cooperates:
+// kProbeLanes lanes read one 32-word window with 16-byte loads (each load
+// instruction covering a contiguous 16 * kProbeLanes bytes of every window
+// it touches) and their partial counts are summed with DPP lane moves.  NT
+// selects non-temporal loads (data lines, no reuse) over cached ones (line
+// heads, kept in L2).  `scr` is this wave's LDS scratch of 4 * NC * 64
+// words.  Must be called by all 64 lanes.
 constexpr uint32_t kNoLine = 0xFFFFFFFFu;
 
 template <int CTRL>
@@ -117,53 +120,63 @@ __device__ __forceinline__ uint32_t count_lt4(u32x4 v, uint32_t x) {
 #define BITS_PROBE_LANES 8
 #endif
 constexpr int kProbeLanes = BITS_PROBE_LANES;        // lanes reading one line
-constexpr int kProbeLoads = 8 / kProbeLanes;         // 16-byte loads per lane per line
-constexpr int kProbeGroups = kWave / kProbeLanes;    // lines per instruction
 
-// Sum over each aligned group of kProbeLanes lanes, in every lane of the group.
+// Sum over each aligned group of L lanes, in every lane of the group.
+template <int L>
 __device__ __forceinline__ uint32_t group_sum(uint32_t t) {
-    if constexpr (kProbeLanes >= 2) t += dpp_u32<0xB1>(t);    // quad_perm [1,0,3,2]
-    if constexpr (kProbeLanes >= 4) t += dpp_u32<0x4E>(t);    // quad_perm [2,3,0,1]
-    if constexpr (kProbeLanes >= 8) t += dpp_u32<0x141>(t);   // row_half_mirror
+    if constexpr (L >= 2) t += dpp_u32<0xB1>(t);    // quad_perm [1,0,3,2]
+    if constexpr (L >= 4) t += dpp_u32<0x4E>(t);    // quad_perm [2,3,0,1]
+    if constexpr (L >= 8) t += dpp_u32<0x141>(t);   // row_half_mirror
     return t;
 }
 
-template <int NC>
+// WIN words per window (32: a 128-byte line; 16: half a line), read by
+// LANES lanes with WIN / (4 LANES) 16-byte loads each.
+template <int NC, bool NT, int WIN = 32, int LANES = kProbeLanes>
 __device__ __forceinline__ void probe_lines(const uint32_t* __restrict__ ks, const uint32_t* __restrict__ ke,
-                                            const uint32_t (&line)[NC], const uint32_t (&x)[NC],
+                                            const uint32_t (&start)[NC], const uint32_t (&x)[NC],
                                             uint32_t (&cnt)[NC], uint32_t* scr) {
+    constexpr int kLanes = LANES;
+    constexpr int kLoads = WIN / 4 / LANES;      // 16-byte loads per lane per window
+    constexpr int kGroups = kWave / LANES;       // windows per instruction
+    static_assert(kLoads >= 1 && WIN % (4 * LANES) == 0, "window geometry");
     const uint32_t lane = threadIdx.x & (kWave - 1);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        // an idle lane probes line 0 against x = 0 (counts nothing, result unused)
-        const bool on = line[c] != kNoLine;
-        scr[(2 * c + 0) * 2 * kWave + 2 * lane] = on ? line[c] : 0u;
+        // an idle lane probes words 0..31 against x = 0 (counts nothing, result unused)
+        const bool on = start[c] != kNoLine;
+        scr[(2 * c + 0) * 2 * kWave + 2 * lane] = on ? start[c] : 0u;
         scr[(2 * c + 0) * 2 * kWave + 2 * lane + 1] = on ? x[c] : 0u;
     }
     wave_lds_sync();
-    const uint32_t sub = lane % kProbeLanes, grp = lane / kProbeLanes;
+    const uint32_t sub = lane % kLanes, grp = lane / kLanes;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const uint32_t* K = (c & 1) ? ke : ks;
-        u32x4 v[kProbeLanes][kProbeLoads];
-        uint32_t xx[kProbeLanes];
+        u32x4 v[kLanes][kLoads];
+        uint32_t xx[kLanes];
 #pragma unroll
-        for (int j = 0; j < kProbeLanes; ++j) {
-            const uint32_t owner = (uint32_t)j * kProbeGroups + grp;
+        for (int j = 0; j < kLanes; ++j) {
+            const uint32_t owner = (uint32_t)j * kGroups + grp;
             const uint2 lx = *reinterpret_cast<const uint2*>(scr + (2 * c + 0) * 2 * kWave + 2 * owner);
             xx[j] = lx.y;
-            // load k covers bytes [16 k L, 16 (k + 1) L) of the line (L lanes), contiguous per group
-            const u32x4* P = reinterpret_cast<const u32x4*>(K + lx.x * 32u) + sub;
+            // load k covers bytes [16 k L, 16 (k + 1) L) of the window (L lanes), contiguous per group
+            const u32x4* P = reinterpret_cast<const u32x4*>(K + lx.x) + sub;
 #pragma unroll
-            for (int k = 0; k < kProbeLoads; ++k) v[j][k] = __builtin_nontemporal_load(P + k * kProbeLanes);
+            for (int k = 0; k < kLoads; ++k) {
+                if constexpr (NT)
+                    v[j][k] = __builtin_nontemporal_load(P + k * kLanes);
+                else
+                    v[j][k] = P[k * kLanes];
+            }
         }
 #pragma unroll
-        for (int j = 0; j < kProbeLanes; ++j) {
-            const uint32_t owner = (uint32_t)j * kProbeGroups + grp;
+        for (int j = 0; j < kLanes; ++j) {
+            const uint32_t owner = (uint32_t)j * kGroups + grp;
             uint32_t t = 0;
 #pragma unroll
-            for (int k = 0; k < kProbeLoads; ++k) t += count_lt4(v[j][k], xx[j]);
-            t = group_sum(t);
+            for (int k = 0; k < kLoads; ++k) t += count_lt4(v[j][k], xx[j]);
+            t = group_sum<LANES>(t);
             if (sub == 0) scr[(2 * c + 1) * 2 * kWave + owner] = t;
         }
     }
@@ -297,16 +310,17 @@ __device__ __forceinline__ void icount_plain(const SearchArgs& sa, const uint32_
     }
 }
 
-// Learned path.  Must be called by all 64 lanes of the wave (line probe).
-// Leaf stage of the learned path for NC chains (even chains search B_S,
-// odd ones B_E): route, evaluate the leaf model, and set either the resolved
-// rank (base, win = false: x <= kmin or x > kmax) or the error window
-// [wl, wr] and the probe line.  Must be called by all 64 lanes.
+// Leaf stage of both learned searches for NC chains (even chains search B_S,
+// odd ones B_E): route each key and evaluate its leaf model.  Per chain:
+// the leaf's rank range [rlo, rhi]; inside = (kmin < x <= kmax); pred = the
+// model's rank for an inside key, else the resolved rank (rhi if x > kmax,
+// rlo if x <= kmin: routing is monotone, so no key of another leaf lies
+// between); err = the leaf's packed error bounds.  Must be called by all 64
+// lanes.
 template <int NC>
-__device__ __forceinline__ void learned_windows(const SearchArgs& sa, uint32_t* scr, const uint32_t (&x)[NC],
-                                                uint32_t (&base)[NC], uint32_t (&len)[NC], uint32_t (&wl)[NC],
-                                                uint32_t (&wr)[NC], uint32_t (&rlo)[NC], uint32_t (&rhi)[NC],
-                                                uint32_t (&ln)[NC], bool (&win)[NC]) {
+__device__ __forceinline__ void leaf_stage(const SearchArgs& sa, uint32_t* scr, const uint32_t (&x)[NC],
+                                           uint32_t (&rlo)[NC], uint32_t (&rhi)[NC], uint32_t (&pred)[NC],
+                                           uint32_t (&err)[NC], bool (&inside)[NC]) {
     uint32_t leaf[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -320,26 +334,43 @@ __device__ __forceinline__ void learned_windows(const SearchArgs& sa, uint32_t* 
         const uint32_t* res = scr + c * kLeafScr + 2 * kWave + 6 * lane;
         const uint2 ra = *reinterpret_cast<const uint2*>(res), rb = *reinterpret_cast<const uint2*>(res + 2),
                     rc = *reinterpret_cast<const uint2*>(res + 4);
-        const uint4 r0 = make_uint4(ra.x, ra.y, rb.x, rb.y);   // kmin kmax rlo cnt
-        const uint4 r1 = make_uint4(rc.x, 0u, rc.y, 0u);       // y - err -
-        rlo[c] = r0.z;
-        rhi[c] = r0.z + r0.w;
-        win[c] = false;
-        base[c] = rlo[c];
+        // ra = {kmin, kmax}, rb = {rlo, cnt}, rc = {y, err}
+        // clamped to [0, n] so that no header value can send a search out of bounds
+        rhi[c] = min(rb.x + rb.y, sa.n);
+        rlo[c] = min(rb.x, rhi[c]);
+        err[c] = rc.y;
+        inside[c] = x[c] > ra.x && x[c] <= ra.y;
+        if (inside[c])
+            pred[c] = min(rlo[c] + (uint32_t)rmi_offset_from_y(__uint_as_float(rc.x), rb.y), rhi[c]);
+        else
+            pred[c] = x[c] > ra.y ? rhi[c] : rlo[c];
+    }
+}
+
+// Windowed learned search, leaf part: either the resolved rank (base,
+// win = false) or the error window [wl, wr] around the prediction and the
+// line to probe first.  Must be called by all 64 lanes.
+template <int NC>
+__device__ __forceinline__ void learned_windows(const SearchArgs& sa, uint32_t* scr, const uint32_t (&x)[NC],
+                                                uint32_t (&base)[NC], uint32_t (&len)[NC], uint32_t (&wl)[NC],
+                                                uint32_t (&wr)[NC], uint32_t (&rlo)[NC], uint32_t (&rhi)[NC],
+                                                uint32_t (&ln)[NC], bool (&win)[NC]) {
+    uint32_t pred[NC], err[NC];
+    leaf_stage<NC>(sa, scr, x, rlo, rhi, pred, err, win);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        base[c] = pred[c];
         len[c] = 0;
         ln[c] = kNoLine;
         wl[c] = wr[c] = 0;
-        if (x[c] > r0.y) {
-            base[c] = rhi[c];
-        } else if (x[c] > r0.x) {
-            win[c] = true;
-            const int32_t pred = (int32_t)r0.z + rmi_offset_from_y(__uint_as_float(r1.x), r0.w);
-            const int32_t lo = pred - (int32_t)(r1.z & 0xFFFFu), hi = pred + (int32_t)(r1.z >> 16);
+        if (win[c]) {
+            const int32_t p = (int32_t)pred[c];
+            const int32_t lo = p - (int32_t)(err[c] & 0xFFFFu), hi = p + (int32_t)(err[c] >> 16);
             wl[c] = (uint32_t)max(lo, (int32_t)rlo[c]);
             wr[c] = (uint32_t)min(hi, (int32_t)rhi[c]);
             if (wr[c] < wl[c]) wr[c] = wl[c];
             base[c] = wl[c];
-            if (wr[c] > wl[c]) ln[c] = min(max((uint32_t)max(pred, 0), wl[c]), wr[c] - 1u) >> 5;
+            if (wr[c] > wl[c]) ln[c] = min(max(pred[c], wl[c]), wr[c] - 1u) >> 5;
         }
     }
 }
@@ -356,7 +387,10 @@ __device__ __forceinline__ void icount_learned(const SearchArgs& sa, uint32_t* s
         x[2 * q + 1] = as[q];
     }
     learned_windows<NC>(sa, scr, x, base, len, wl, wr, rlo, rhi, ln, win);
-    probe_lines<NC>(sa.bs, sa.be, ln, x, pc, scr);
+    uint32_t lw[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) lw[c] = ln[c] == kNoLine ? kNoLine : ln[c] * 32u;
+    probe_lines<NC, true>(sa.bs, sa.be, lw, x, pc, scr);
     bool exact[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -409,6 +443,128 @@ __device__ __forceinline__ void icount_learned(const SearchArgs& sa, uint32_t* s
     for (int q = 0; q < QPL; ++q) {
         const uint32_t first = (ae[q] == 0xFFFFFFFFu) ? sa.n : base[2 * q];
         cnt[q] = first - base[2 * q + 1];
+    }
+}
+
+// Learned search through the line heads (H[j] = K[32 j], the first key of
+// every 128-byte line of a sorted array, padded with 0xFFFFFFFF).  With
+// r = #{K < x} the lower bound and j = #{H < x} = ceil(r / 32), the lower
+// bound lies in line j - 1: r = 32 (j - 1) + #{keys < x in that line}, or
+// r = 0 when j = 0.  Per chain:
+//   1. leaf model -> predicted rank -> line p = pred / 32;
+//   2. one cooperative probe of a window of kHeadWin heads with p at least
+//      kHeadLead lines from either end (cached loads: a workgroup that serves
+//      one part of the key range keeps that part's heads in its L2) gives j
+//      exactly when 0 < count < kHeadWin (or the window starts at 0);
+//   3. otherwise the window next to it on the side the count points to is
+//      probed (only if some lane of the wave needs it), and what is still
+//      unresolved is bisected over the heads of the leaf's rank range (the
+//      fallback counter counts these);
+//   4. one cooperative non-temporal probe of line j - 1 gives r.
+// Exact whatever the model predicts (no verification step), and every read
+// stays inside the arrays whatever the leaf records hold.  Must be called by
+// all 64 lanes.
+#ifndef BITS_HEAD_WIN
+#define BITS_HEAD_WIN 16
+#endif
+#ifndef BITS_HEAD_ALIGN
+#define BITS_HEAD_ALIGN 8
+#endif
+#ifndef BITS_HEAD_LEAD
+#define BITS_HEAD_LEAD 4
+#endif
+constexpr uint32_t kHeadWin = BITS_HEAD_WIN;      // heads per window
+constexpr uint32_t kHeadAlign = BITS_HEAD_ALIGN;  // window start is a multiple of this (>= 4: 16-byte loads)
+constexpr uint32_t kHeadLead = BITS_HEAD_LEAD;    // the predicted line sits >= this many lines into the window
+constexpr int kHeadLanes = kHeadWin == 32 ? kProbeLanes : 4;
+// windows reach at most 2 kHeadWin - kHeadLead heads past the predicted line
+// (second window on the right), which the >= 32 padding heads cover
+static_assert(kHeadLead + kHeadAlign <= kHeadWin && 2 * kHeadWin <= 32 + kHeadLead && kHeadAlign % 4 == 0,
+              "head window");
+
+// j from a window count: resolved (0 < cnt < kHeadWin, or cnt = 0 at the
+// start of the array), else left (j <= w) or right (j >= w + kHeadWin).
+enum : uint32_t { kHeadHit = 0, kHeadLeft = 1, kHeadRight = 2 };
+__device__ __forceinline__ uint32_t head_outcome(uint32_t w, uint32_t cnt) {
+    if (cnt >= kHeadWin) return kHeadRight;
+    return (cnt == 0u && w != 0u) ? kHeadLeft : kHeadHit;
+}
+
+template <int QPL>
+__device__ __forceinline__ void icount_heads(const SearchArgs& sa, uint32_t* scr, const uint32_t (&as)[QPL],
+                                             const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL]) {
+    constexpr int NC = 2 * QPL;
+    uint32_t x[NC], rlo[NC], rhi[NC], pred[NC], err[NC], w[NC], pc[NC], st[NC];
+    bool inside[NC];
+#pragma unroll
+    for (int q = 0; q < QPL; ++q) {
+        x[2 * q] = ae[q] + 1u;
+        x[2 * q + 1] = as[q];
+    }
+    leaf_stage<NC>(sa, scr, x, rlo, rhi, pred, err, inside);
+    const uint32_t m = (sa.n + 31u) >> 5;     // heads in use
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const uint32_t p = pred[c] >> 5;
+        w[c] = inside[c] ? ((p > kHeadLead ? p - kHeadLead : 0u) & ~(kHeadAlign - 1u)) : kNoLine;
+    }
+    probe_lines<NC, false, kHeadWin, kHeadLanes>(sa.hs, sa.he, w, x, pc, scr);
+    bool again = false;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        st[c] = w[c] == kNoLine ? kHeadHit : head_outcome(w[c], pc[c]);
+        pc[c] = w[c] + pc[c];                 // j when resolved
+        if (st[c] == kHeadLeft) w[c] = w[c] >= kHeadWin ? w[c] - kHeadWin : 0u;
+        if (st[c] == kHeadRight) w[c] += kHeadWin;
+        again |= st[c] != kHeadHit;
+    }
+    uint32_t j[NC], jl[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        j[c] = pc[c];
+        jl[c] = 0;
+    }
+    if (__ballot(again)) {
+        uint32_t w2[NC], pc2[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) w2[c] = st[c] != kHeadHit ? w[c] : kNoLine;
+        probe_lines<NC, false, kHeadWin, kHeadLanes>(sa.hs, sa.he, w2, x, pc2, scr);
+        uint32_t nmiss = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (st[c] == kHeadHit) continue;
+            const uint32_t o = head_outcome(w2[c], pc2[c]);
+            if (o == kHeadHit) {
+                j[c] = w2[c] + pc2[c];
+                continue;
+            }
+            // still unresolved: j lies in [ceil(rlo/32), ceil(rhi/32)] (rlo <= r <= rhi),
+            // on the side of w2 the count points to
+            const uint32_t hi = min((rhi[c] + 31u) >> 5, m), lo = min((rlo[c] + 31u) >> 5, hi);
+            uint32_t a = lo, b = hi;
+            if (o == kHeadLeft && w2[c] >= lo && w2[c] <= hi) b = w2[c];
+            if (o == kHeadRight && w2[c] + kHeadWin >= lo && w2[c] + kHeadWin <= hi) a = w2[c] + kHeadWin;
+            j[c] = a;
+            jl[c] = b - a;
+            ++nmiss;
+        }
+        if (nmiss) {
+            atomicAdd(sa.fallbacks, (unsigned long long)nmiss);
+            bisect_multi<NC>(sa.hs, sa.he, j, jl, x, 32u);
+        }
+    }
+    uint32_t dw[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        dw[c] = (inside[c] && j[c] != 0u) ? (min(j[c], m) - 1u) * 32u : kNoLine;
+    probe_lines<NC, true>(sa.bs, sa.be, dw, x, pc, scr);
+    uint32_t r[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) r[c] = !inside[c] ? pred[c] : (dw[c] == kNoLine ? 0u : dw[c] + pc[c]);
+#pragma unroll
+    for (int q = 0; q < QPL; ++q) {
+        const uint32_t first = (ae[q] == 0xFFFFFFFFu) ? sa.n : r[2 * q];
+        cnt[q] = first - r[2 * q + 1];
     }
 }
 
@@ -472,21 +628,41 @@ BITS_SEARCH_KERNEL k_count(SearchArgs sa, const uint32_t* __restrict__ a_start,
 }
 
 // ------------------------------------------------------------------ Monte-Carlo
-// Work item = (tile of blockDim*QPL queries, chunk of consecutive shuffles);
-// items are walked by a persistent grid.  A workgroup reads its tile's
-// per-query table once per item and runs every shuffle of the chunk on it.
-// Query i of shuffle s starts at off_i + floor(u * span_i / 2^64), u = the
-// first two Philox words of counter g = (s0 + s) * na + i.  Per-shuffle wave
-// sums are added in LDS and flushed with one global atomic per shuffle per
-// item.  OBSERVED counts the unshuffled queries instead (same exclusion of
-// queries with span 0, i.e. outside their chromosome).
+// The per-query table (off, span, len, idx) is grouped by chromosome (see
+// k_mc_prepare): position j holds query idx[j].  Work item = (tile of
+// blockDim*QPL table positions, chunk of consecutive shuffles), walked by a
+// persistent grid.  A workgroup reads its tile's table entries once per item
+// and runs every shuffle of the chunk on them.  Query i of shuffle s starts at
+// off_i + floor(u * span_i / 2^64), u = the first two Philox words of counter
+// g = (s0 + s) * na + i.  Per-shuffle wave sums are added in LDS and flushed
+// with one global atomic per shuffle per item.  OBSERVED counts the
+// unshuffled queries instead (same exclusion of queries with span 0, i.e.
+// outside their chromosome).
+//
+// XCD-aware split: workgroups are dispatched round-robin over the 8 XCDs,
+// so workgroup b runs on XCD b mod 8.  The tiles are cut into 8 contiguous
+// groups and group x is served only by workgroups b = x (mod 8).  A shuffle
+// keeps every query inside its chromosome, and the table is grouped by
+// chromosome, so each XCD searches one contiguous part of B and its L2 holds
+// that part's leaves and line heads.  (With another placement the split only
+// costs locality, never correctness.)
 constexpr uint32_t kMaxChunk = 64;
+constexpr uint32_t kXcds = 8;
+
+template <int QPL, bool LEARNED>
+__device__ __forceinline__ void icount_mc(const SearchArgs& sa, uint32_t* lds, const uint32_t (&as)[QPL],
+                                          const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL]) {
+    if constexpr (LEARNED)
+        icount_heads<QPL>(sa, lds + (threadIdx.x / kWave) * probe_scratch_words(QPL), as, ae, cnt);
+    else
+        icount_plain<QPL>(sa, lds, as, ae, cnt);
+}
 
 template <int QPL, bool LEARNED, bool OBSERVED>
 BITS_SEARCH_KERNEL k_mc(SearchArgs sa, const uint32_t* __restrict__ a_start, const uint32_t* __restrict__ a_end,
          const uint32_t* __restrict__ off, const uint32_t* __restrict__ span, const uint32_t* __restrict__ len,
-         uint64_t na, uint64_t seed, uint64_t s0, uint64_t nshuf, uint64_t tiles, uint32_t chunk,
-         unsigned long long* __restrict__ totals) {
+         const uint32_t* __restrict__ idx, uint64_t na, uint64_t seed, uint64_t s0, uint64_t nshuf, uint64_t tiles,
+         uint32_t chunk, unsigned long long* __restrict__ totals) {
     extern __shared__ uint32_t lds[];
     __shared__ unsigned long long acc[kMaxChunk];
     if (!LEARNED) stage_tree(lds, sa.tree, sa.tree_stride, sa.depth);
@@ -494,25 +670,31 @@ BITS_SEARCH_KERNEL k_mc(SearchArgs sa, const uint32_t* __restrict__ a_start, con
     __syncthreads();
     const uint64_t tile = (uint64_t)blockDim.x * QPL;
     const uint64_t nchunks = (nshuf + chunk - 1) / chunk;
-    const uint64_t nitems = tiles * nchunks;
+    const uint32_t ng = (gridDim.x >= kXcds && tiles >= kXcds) ? kXcds : 1u;
+    const uint32_t grp = blockIdx.x % ng, slot = blockIdx.x / ng;
+    const uint32_t nslots = (gridDim.x - grp + ng - 1) / ng;   // workgroups b < gridDim with b = grp (mod ng)
+    const uint64_t t_lo = tiles * grp / ng, gtiles = tiles * (grp + 1) / ng - t_lo;
+    const uint64_t nitems = gtiles * nchunks;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const uint64_t kc = it / tiles;
-        const uint64_t t = it - kc * tiles;
+    for (uint64_t it = slot; it < nitems; it += nslots) {
+        const uint64_t kc = it / gtiles;
+        const uint64_t t = t_lo + (it - kc * gtiles);
         uint32_t qo[QPL], qs[QPL], ql[QPL];
         uint64_t qi[QPL];
         bool valid[QPL];
 #pragma unroll
         for (int q = 0; q < QPL; ++q) {
-            qi[q] = t * tile + (uint64_t)q * blockDim.x + threadIdx.x;
-            qs[q] = qi[q] < na ? span[qi[q]] : 0u;
+            const uint64_t pos = t * tile + (uint64_t)q * blockDim.x + threadIdx.x;
+            const bool in = pos < na;
+            qs[q] = in ? span[pos] : 0u;
+            qi[q] = in ? idx[pos] : 0u;
             valid[q] = qs[q] != 0u;
             if (OBSERVED) {
                 qo[q] = valid[q] ? a_start[qi[q]] : 0u;
                 ql[q] = valid[q] ? a_end[qi[q]] : 0u;
             } else {
-                qo[q] = valid[q] ? off[qi[q]] : 0u;
-                ql[q] = valid[q] ? len[qi[q]] : 1u;
+                qo[q] = valid[q] ? off[pos] : 0u;
+                ql[q] = valid[q] ? len[pos] : 1u;
             }
         }
         const uint64_t sb = kc * chunk;
@@ -534,7 +716,7 @@ BITS_SEARCH_KERNEL k_mc(SearchArgs sa, const uint32_t* __restrict__ a_start, con
                     ae[q] = valid[q] ? as[q] + ql[q] - 1u : 0u;
                 }
             }
-            icount<QPL, LEARNED>(sa, lds, as, ae, cnt);
+            icount_mc<QPL, LEARNED>(sa, lds, as, ae, cnt);
             uint64_t sum = 0;
 #pragma unroll
             for (int q = 0; q < QPL; ++q) sum += valid[q] ? cnt[q] : 0u;
@@ -556,27 +738,80 @@ struct ChromTab {
     uint32_t off[BITS_MAX_CHROM + 1];   // off[c] = sum of lengths before c; off[n] = genome size
 };
 
-// Per-query (chromosome offset, number of legal starts, length), computed
-// once and reused by every shuffle.  span = 0 marks a query outside its
-// chromosome (or start > end).
-__global__ void k_mc_prepare(const uint32_t* __restrict__ a_start, const uint32_t* __restrict__ a_end, uint64_t na,
-                             ChromTab ct, uint32_t* __restrict__ off, uint32_t* __restrict__ span,
-                             uint32_t* __restrict__ len, uint32_t* status) {
-    uint32_t bad = 0;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t s = a_start[i], e = a_end[i];
-        uint32_t lo = 0, hi = ct.n;          // chromosome = last c with off[c] <= s
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (ct.off[mid] <= s) lo = mid; else hi = mid;
+// Chromosome of a global coordinate: the last c with off[c] <= s.
+__device__ __forceinline__ uint32_t chrom_of(const ChromTab& ct, uint32_t s) {
+    uint32_t lo = 0, hi = ct.n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (ct.off[mid] <= s) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Per-chromosome query counts (hist zeroed by the caller).
+__global__ void __launch_bounds__(256) k_mc_hist(const uint32_t* __restrict__ a_start, uint64_t na, ChromTab ct,
+                                                 uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[BITS_MAX_CHROM];
+    for (uint32_t k = threadIdx.x; k < BITS_MAX_CHROM; k += blockDim.x) h[k] = 0u;
+    __syncthreads();
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na; i += (uint64_t)gridDim.x * blockDim.x)
+        atomicAdd(&h[chrom_of(ct, a_start[i])], 1u);
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < ct.n; k += blockDim.x)
+        if (h[k]) atomicAdd(&hist[k], h[k]);
+}
+
+// cursor[c] = queries on chromosomes before c (one lane; at most 256 bins).
+__global__ void k_mc_scan(const uint32_t* __restrict__ hist, uint32_t n, uint32_t* __restrict__ cursor) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        uint32_t acc = 0;
+        for (uint32_t k = 0; k < n; ++k) {
+            cursor[k] = acc;
+            acc += hist[k];
         }
-        const uint32_t c = lo;
-        const bool ok = s <= e && s >= ct.off[c] && (uint64_t)e < (uint64_t)ct.off[c + 1];
-        const uint32_t L = e - s + 1u;
-        off[i] = ct.off[c];
-        len[i] = ok ? L : 1u;
-        span[i] = ok ? (ct.off[c + 1] - ct.off[c]) - L + 1u : 0u;
-        if (!ok) bad |= (s > e) ? BITS_FLAG_INTERVAL : BITS_FLAG_CHROM;
+    }
+}
+
+// Per-query (chromosome offset, number of legal starts, length, index),
+// computed once and reused by every shuffle, stored grouped by chromosome:
+// each round of blockDim queries takes one slot range per chromosome from
+// `cursor` and places its queries there.  The order inside a chromosome's
+// range depends on scheduling; the totals do not (sums over the queries,
+// each drawing from its own index).  span = 0 marks a query outside its
+// chromosome (or start > end).
+__global__ void __launch_bounds__(1024) k_mc_prepare(const uint32_t* __restrict__ a_start,
+                                                     const uint32_t* __restrict__ a_end, uint64_t na, ChromTab ct,
+                                                     uint32_t* __restrict__ cursor, uint32_t* __restrict__ off,
+                                                     uint32_t* __restrict__ span, uint32_t* __restrict__ len,
+                                                     uint32_t* __restrict__ idx, uint32_t* status) {
+    __shared__ uint32_t cnt[BITS_MAX_CHROM], base[BITS_MAX_CHROM];
+    uint32_t bad = 0;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < na; i0 += (uint64_t)gridDim.x * blockDim.x) {
+        for (uint32_t k = threadIdx.x; k < ct.n; k += blockDim.x) cnt[k] = 0u;
+        __syncthreads();
+        const uint64_t i = i0 + threadIdx.x;
+        uint32_t s = 0, e = 0, c = 0, r = 0;
+        if (i < na) {
+            s = a_start[i];
+            e = a_end[i];
+            c = chrom_of(ct, s);
+            r = atomicAdd(&cnt[c], 1u);
+        }
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < ct.n; k += blockDim.x)
+            if (cnt[k]) base[k] = atomicAdd(&cursor[k], cnt[k]);
+        __syncthreads();
+        if (i < na) {
+            const bool ok = s <= e && s >= ct.off[c] && (uint64_t)e < (uint64_t)ct.off[c + 1];
+            const uint32_t L = e - s + 1u;
+            const uint32_t pos = base[c] + r;
+            off[pos] = ct.off[c];
+            len[pos] = ok ? L : 1u;
+            span[pos] = ok ? (ct.off[c + 1] - ct.off[c]) - L + 1u : 0u;
+            idx[pos] = (uint32_t)i;
+            if (!ok) bad |= (s > e) ? BITS_FLAG_INTERVAL : BITS_FLAG_CHROM;
+        }
+        __syncthreads();
     }
     if (bad) atomicOr(status, bad);
 }
@@ -845,30 +1080,35 @@ static int fill_chrom_tab(const uint32_t* chrom_len, uint32_t n_chrom, ChromTab*
 }
 
 hipError_t launch_mc_prepare(const uint32_t* as, const uint32_t* ae, uint64_t na, const uint32_t* chrom_len,
-                             uint32_t n_chrom, uint32_t* off, uint32_t* span, uint32_t* len, uint32_t* status,
-                             hipStream_t s) {
+                             uint32_t n_chrom, const McTable& tab, uint32_t* status, hipStream_t s) {
     ChromTab ct;
     if (fill_chrom_tab(chrom_len, n_chrom, &ct) != BITS_OK) return hipErrorInvalidValue;
     if (!na) return hipSuccess;
+    hipError_t e = launch_fill_u32(tab.hist, n_chrom, 0u, s);
+    if (e != hipSuccess) return e;
     uint64_t g = (na + 255) / 256;
-    if (g > 8192) g = 8192;
-    hipLaunchKernelGGL(k_mc_prepare, dim3((uint32_t)g), dim3(256), 0, s, as, ae, na, ct, off, span, len, status);
+    if (g > 2048) g = 2048;
+    hipLaunchKernelGGL(k_mc_hist, dim3((uint32_t)g), dim3(256), 0, s, as, na, ct, tab.hist);
+    hipLaunchKernelGGL(k_mc_scan, dim3(1), dim3(64), 0, s, tab.hist, n_chrom, tab.cursor);
+    g = (na + 1023) / 1024;
+    if (g > 1024) g = 1024;
+    hipLaunchKernelGGL(k_mc_prepare, dim3((uint32_t)g), dim3(1024), 0, s, as, ae, na, ct, tab.cursor, tab.off,
+                       tab.span, tab.len, tab.idx, status);
     return hipGetLastError();
 }
 
 template <int QPL, bool LEARNED>
 static hipError_t launch_mc_t(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
-                              const uint32_t* off, const uint32_t* span, const uint32_t* len, uint64_t na,
-                              uint64_t seed, uint64_t s0, uint64_t nshuf, unsigned long long* totals,
-                              unsigned long long* observed, hipStream_t s) {
+                              const McTable& tab, uint64_t na, uint64_t seed, uint64_t s0, uint64_t nshuf,
+                              unsigned long long* totals, unsigned long long* observed, hipStream_t s) {
     const size_t lds = search_lds_bytes(LEARNED, sa.depth, QPL, cfg.block);
     const uint64_t tile = (uint64_t)cfg.block * QPL;
     const uint64_t tps = (na + tile - 1) / tile;
     if (observed) {
         const void* ko = (const void*)k_mc<QPL, LEARNED, true>;
         const uint32_t go = persistent_grid(ko, cfg, lds, tps);
-        hipLaunchKernelGGL((k_mc<QPL, LEARNED, true>), dim3(go), dim3(cfg.block), lds, s, sa, as, ae, off, span,
-                           len, na, seed, s0, (uint64_t)1, tps, 1u, observed);
+        hipLaunchKernelGGL((k_mc<QPL, LEARNED, true>), dim3(go), dim3(cfg.block), lds, s, sa, as, ae, tab.off,
+                           tab.span, tab.len, tab.idx, na, seed, s0, (uint64_t)1, tps, 1u, observed);
     }
     if (nshuf) {
         const void* km = (const void*)k_mc<QPL, LEARNED, false>;
@@ -876,25 +1116,24 @@ static hipError_t launch_mc_t(const SearchArgs& sa, const LaunchCfg& cfg, const 
         // shuffles per work item: as many as keep >= 8 items per workgroup
         uint32_t chunk = kMaxChunk;
         while (chunk > 1 && tps * ((nshuf + chunk - 1) / chunk) < 8ull * gm) chunk >>= 1;
-        hipLaunchKernelGGL((k_mc<QPL, LEARNED, false>), dim3(gm), dim3(cfg.block), lds, s, sa, as, ae, off, span,
-                           len, na, seed, s0, nshuf, tps, chunk, totals);
+        hipLaunchKernelGGL((k_mc<QPL, LEARNED, false>), dim3(gm), dim3(cfg.block), lds, s, sa, as, ae, tab.off,
+                           tab.span, tab.len, tab.idx, na, seed, s0, nshuf, tps, chunk, totals);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_mc(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
-                     const uint32_t* off, const uint32_t* span, const uint32_t* len, uint64_t na, uint64_t seed,
-                     uint64_t s0, uint64_t nshuf, unsigned long long* totals, unsigned long long* observed,
-                     hipStream_t s) {
+                     const McTable& tab, uint64_t na, uint64_t seed, uint64_t s0, uint64_t nshuf,
+                     unsigned long long* totals, unsigned long long* observed, hipStream_t s) {
     if (!na) return hipSuccess;
     const bool L = cfg.path == BITS_PATH_LEARNED;
     switch (cfg.qpl) {
-        case 1: return L ? launch_mc_t<1, true>(sa, cfg, as, ae, off, span, len, na, seed, s0, nshuf, totals, observed, s)
-                         : launch_mc_t<1, false>(sa, cfg, as, ae, off, span, len, na, seed, s0, nshuf, totals, observed, s);
-        case 4: return L ? launch_mc_t<4, true>(sa, cfg, as, ae, off, span, len, na, seed, s0, nshuf, totals, observed, s)
-                         : launch_mc_t<4, false>(sa, cfg, as, ae, off, span, len, na, seed, s0, nshuf, totals, observed, s);
-        default: return L ? launch_mc_t<2, true>(sa, cfg, as, ae, off, span, len, na, seed, s0, nshuf, totals, observed, s)
-                          : launch_mc_t<2, false>(sa, cfg, as, ae, off, span, len, na, seed, s0, nshuf, totals, observed, s);
+        case 1: return L ? launch_mc_t<1, true>(sa, cfg, as, ae, tab, na, seed, s0, nshuf, totals, observed, s)
+                         : launch_mc_t<1, false>(sa, cfg, as, ae, tab, na, seed, s0, nshuf, totals, observed, s);
+        case 4: return L ? launch_mc_t<4, true>(sa, cfg, as, ae, tab, na, seed, s0, nshuf, totals, observed, s)
+                         : launch_mc_t<4, false>(sa, cfg, as, ae, tab, na, seed, s0, nshuf, totals, observed, s);
+        default: return L ? launch_mc_t<2, true>(sa, cfg, as, ae, tab, na, seed, s0, nshuf, totals, observed, s)
+                          : launch_mc_t<2, false>(sa, cfg, as, ae, tab, na, seed, s0, nshuf, totals, observed, s);
     }
 }
 

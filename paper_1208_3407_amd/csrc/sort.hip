@@ -325,6 +325,13 @@ __global__ void k_build_tree(const uint32_t* __restrict__ keys, uint64_t n, uint
     }
 }
 
+// Line heads: the first key of every 128-byte line, then +inf padding.
+__global__ void k_build_heads(const uint32_t* __restrict__ keys, uint64_t n, uint64_t hl, uint32_t* __restrict__ heads) {
+    const uint64_t m = (n + 31) / 32;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < hl; j += (uint64_t)gridDim.x * blockDim.x)
+        heads[j] = j < m ? keys[32 * j] : 0xFFFFFFFFu;
+}
+
 struct WsLayout {
     size_t descs, plan, seg_hist, seg_pre, H, ping, total;
 };
@@ -415,6 +422,14 @@ hipError_t launch_build_tree(const uint32_t* keys, uint64_t n, uint32_t depth, u
     const uint32_t m = 1u << depth;
     const uint32_t g = (m + 255) / 256;
     hipLaunchKernelGGL(k_build_tree, dim3(g), dim3(256), 0, s, keys, n, depth, tree);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_heads(const uint32_t* keys, uint64_t n, uint32_t* heads, hipStream_t s) {
+    const uint64_t hl = heads_len(n);
+    uint64_t g = (hl + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_build_heads, dim3((uint32_t)g), dim3(256), 0, s, keys, n, hl, heads);
     return hipGetLastError();
 }
 

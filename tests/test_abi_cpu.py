@@ -51,8 +51,8 @@ def test_ref_init_carves_block_on_host(lib):
     class Ref(ctypes.Structure):
         _fields_ = [("n", ctypes.c_uint64), ("depth", ctypes.c_uint32), ("learned", ctypes.c_uint32),
                     ("bs", ctypes.c_void_p), ("be", ctypes.c_void_p), ("tree", ctypes.c_void_p),
-                    ("rmi", ctypes.c_void_p), ("status", ctypes.c_void_p), ("block", ctypes.c_void_p),
-                    ("block_bytes", ctypes.c_size_t)]
+                    ("rmi", ctypes.c_void_p), ("heads", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                    ("block", ctypes.c_void_p), ("block_bytes", ctypes.c_size_t)]
     sz = ctypes.c_size_t(0)
     assert lib.bits_ref_bytes(ctypes.c_uint64(100), 13, 0, ctypes.byref(sz)) == 0
     r = Ref()
@@ -64,6 +64,16 @@ def test_ref_init_carves_block_on_host(lib):
     assert lib.bits_ref_init(ctypes.c_void_p(base), ctypes.c_size_t(sz.value - 1), ctypes.c_uint64(100), 13, 0,
                              ctypes.byref(r)) == 4
     assert lib.bits_ref_init(ctypes.c_void_p(base + 4), sz, ctypes.c_uint64(100), 13, 0, ctypes.byref(r)) == 1
+    assert r.rmi is None and r.heads is None
+    # learned: rmi (2 models of 128 + 4096 * 128 bytes), then the two line-head
+    # arrays (ceil(n/32) heads + >= 32 padding, whole 128-byte lines), then B_S, B_E
+    n = 100_000
+    assert lib.bits_ref_bytes(ctypes.c_uint64(n), 13, 1, ctypes.byref(sz)) == 0
+    assert lib.bits_ref_init(ctypes.c_void_p(base), sz, ctypes.c_uint64(n), 13, 1, ctypes.byref(r)) == 0
+    hl = ((n + 31) // 32 + 32 + 31) // 32 * 32
+    assert r.learned == 1 and r.heads >= r.rmi + 2 * (128 + 4096 * 128)
+    assert r.bs >= r.heads + 2 * hl * 4 and r.heads % 256 == 0
+    assert r.be + 4 * n <= base + sz.value
 
 
 def test_bad_arguments_rejected_before_any_device_work(lib):

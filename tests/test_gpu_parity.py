@@ -298,3 +298,77 @@ def test_learned_windows_hold_every_key():
             rank = np.searchsorted(keys, keys, side="left")
             bad = np.flatnonzero((rank < lo) | (rank > hi))
             assert bad.size == 0, (which, bad[:5], rank[bad[:5]], lo[bad[:5]], hi[bad[:5]])
+
+
+def test_line_heads():
+    """Line heads: the first key of every 128-byte line of each sorted array,
+    then at least 32 entries of +inf up to whole lines."""
+    note("case: line heads")
+    for nb in (1, 31, 32, 33, 1000, 70_001):
+        r = np.random.default_rng(nb)
+        b_s = r.integers(0, 10**7, nb).astype(np.uint32)
+        b_e = b_s + r.integers(0, 500, nb).astype(np.uint32)
+        ref = bits.bits_sort_ref(up(b_s), up(b_e), learned=True, train={"epochs": 0})
+        H = down(ref.heads())
+        hl, m = ref.heads_len(), (nb + 31) // 32
+        assert hl % 32 == 0 and hl - m >= 32
+        for a, keys in enumerate((np.sort(b_s), np.sort(b_e))):
+            assert np.array_equal(H[a, :m], keys[::32]), nb
+            assert np.all(H[a, m:] == 0xFFFFFFFF), nb
+
+
+def test_monte_carlo_grid_shapes():
+    """The Monte-Carlo kernel splits its tiles over 8 workgroup groups (one
+    per XCD) when the grid has >= 8 workgroups and runs one group otherwise;
+    totals must not depend on either, nor on uneven groups."""
+    note("case: MC grid shapes")
+    lengths, A, B = datagen.w2_sets(seed=3, n_a=20_000, n_b=100_000)
+    a_s, a_e, oa_s, oa_e = project_both(lengths, A)
+    b_s, b_e, ob_s, ob_e = project_both(lengths, B)
+    prep = oracle.mc_prepare(lengths, oa_s, oa_e)
+    exp = oracle.mc_totals(np.sort(ob_s), np.sort(ob_e), prep, 11, 5, 17, threads=8)
+    obs = oracle.counter(oa_s, oa_e, ob_s, ob_e)[1]
+    ref = bits.bits_sort_ref(b_s, b_e, learned=True, train={"epochs": 20})
+    for grid in (1, 3, 8, 13, 64):
+        for path in (bits.BITS_PATH_PLAIN, bits.BITS_PATH_LEARNED):
+            lp = {"grid": grid, "path": path, "block": 256, "qpl": 1}
+            note("  launch %s" % lp)
+            mc = bits.bits_mc_pvalue(ref, a_s, a_e, lengths, seed=11, s0=5, s1=17, launch=lp)
+            assert np.array_equal(down(mc.totals), exp), lp
+            assert int(down(mc.observed)[0]) == obs, lp
+    assert bits.bits_get_status(ref) == 0
+
+
+@pytest.mark.parametrize("b2", [0.0, 1.0])
+def test_broken_model_stays_exact(b2):
+    """Overwrite every leaf model with a constant (weights 0, b2 = 0 or 1,
+    error bounds 0: every key is predicted at its leaf's first or last rank)
+    in the caller-owned block.  Counts and Monte-Carlo totals must stay exact
+    through the fallbacks (windowed path: verification -> bisection of the
+    leaf; Monte-Carlo: head window miss -> bisection of the leaf's heads)."""
+    note("case: broken model b2=%g" % b2)
+    lengths, A, B = datagen.w2_sets(seed=5, n_a=4000, n_b=4_000_000)
+    a_s, a_e, oa_s, oa_e = project_both(lengths, A)
+    b_s, b_e, ob_s, ob_e = project_both(lengths, B)
+    ref = bits.bits_sort_ref(b_s, b_e, learned=True, train={"epochs": 10})
+    raw = ref.rmi_bytes()
+    for a in range(2):
+        base = a * bits.RMI_MODEL_BYTES + bits.RMI_HEADER_BYTES
+        words = raw[base:base + 4096 * bits.RMI_LEAF_BYTES].view(torch.int32).view(4096, 32)
+        for w in (2, 3, 6, 7, 10, 11, 14, 15):           # binary16 w1 of units 0..15
+            words[:, w] = 0
+        words[:, 16:32] = 0                              # binary16 b1 and w2
+        words[:, 9] = int(np.float32(b2).view(np.int32))  # b2
+        words[:, 12] = 0                                 # error bounds
+    torch.cuda.synchronize()
+    fb0 = bits.bits_rmi_info(ref)["fallbacks"]
+    exp_c, exp_t = oracle.counter(oa_s, oa_e, ob_s, ob_e, threads=8)
+    c, t = bits.bits_count_per_query(ref, a_s, a_e, launch={"path": bits.BITS_PATH_LEARNED})
+    assert np.array_equal(down(c), exp_c) and int(down(t)[0]) == exp_t
+    prep = oracle.mc_prepare(lengths, oa_s, oa_e)
+    exp = oracle.mc_totals(np.sort(ob_s), np.sort(ob_e), prep, 7, 0, 6, threads=8)
+    mc = bits.bits_mc_pvalue(ref, a_s, a_e, lengths, seed=7, s0=0, s1=6, launch={"path": bits.BITS_PATH_LEARNED})
+    assert np.array_equal(down(mc.totals), exp)
+    assert int(down(mc.observed)[0]) == exp_t
+    assert bits.bits_rmi_info(ref)["fallbacks"] > fb0
+    assert bits.bits_get_status(ref) == 0
