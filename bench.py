@@ -31,15 +31,15 @@ N_A = 50_000_000
 N_MC = 1_000_000
 N_SHUF = 1_000
 MC_SEED = 7
-# Bytes per A-interval evaluation moved by the search (byte model of the
-# design notes): 12 B compulsory + two searches of ~1.25 128-byte lines each
-# through the learned index; two searches of ~3 lines each on the plain path.
-BYTES_PER_EVAL_LEARNED = 330.0
-BYTES_PER_EVAL_PLAIN = 780.0
+# Algorithmic HBM bytes per Monte-Carlo evaluation (one shuffled A-interval):
+# the learned search through the line heads reads exactly one 128-byte line
+# of B_S and one of B_E (leaf records and line heads are L2-resident); the
+# 16-byte query-table entry is read once per chunk of up to 64 shuffles.
+BYTES_PER_EVAL_LEARNED = 256.0
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_mc_learned_w4.json")
 # launch shapes the autotuner picked on MI355X for this workload (used with --no-autotune)
-RECORDED_LEARNED = {"block": 1024, "qpl": 1, "depth": 0, "grid": 0, "path": 2}
+RECORDED_LEARNED = {"block": 512, "qpl": 1, "depth": 0, "grid": 0, "path": 2}
 RECORDED_PLAIN = {"block": 256, "qpl": 1, "depth": 13, "grid": 0, "path": 1}
 KERNEL_SOURCES = ["paper_1208_3407_amd/csrc/search.hip", "paper_1208_3407_amd/csrc/bits_internal.hpp"]
 
