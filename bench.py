@@ -30,6 +30,7 @@ N_B = 50_000_000
 N_A = 50_000_000
 N_MC = 1_000_000
 N_SHUF = 1_000
+N_ENUM = 10_000_000   # A-intervals enumerated against the full B (outside the timed region)
 MC_SEED = 7
 # Algorithmic HBM bytes per Monte-Carlo evaluation (one shuffled A-interval):
 # the learned search through the line heads reads exactly one 128-byte line
@@ -244,6 +245,37 @@ def main():
     agree = (plain_total == learned_total) and np.array_equal(mc_plain.totals.cpu().numpy(), mc_totals)
     info = bits.bits_rmi_info(ref)
 
+    # enumeration (sub-problem 4) of the first N_ENUM A-intervals against B, outside the timed region
+    b_s, b_e = bits.bits_project(lengths, *dB)
+    ea_s, ea_e = a_s[:N_ENUM], a_e[:N_ENUM]
+    t_index = timed(lambda: bits.bits_enum_index_build(b_s, b_e), reps=2)
+    index = bits.bits_enum_index_build(b_s, b_e)
+    t_ecount = timed(lambda: bits.bits_enum_counts(ref, ea_s, ea_e, launch=lp_learned))
+    e_counts, e_first, offsets = bits.bits_enum_counts(ref, ea_s, ea_e, launch=lp_learned)
+    n_pairs = int(offsets[-1].item())
+    e_status = torch.zeros(1, dtype=torch.uint32, device=dev)
+    pairs = {}
+
+    def run_enum():
+        pairs["ab"] = bits.bits_enumerate(index, ea_s, ea_e, e_counts, offsets, first=e_first, max_pairs=n_pairs,
+                                          status=e_status)
+    t_enum = timed(run_enum)
+    pa, pb = pairs["ab"]
+    pick = torch.randint(0, max(n_pairs, 1), (min(n_pairs, 100_000),), device=dev)
+
+    def gather_u32(t, idx):   # uint32 values at idx, as int64 (torch indexes int32, not uint32)
+        return t.view(torch.int32)[idx].long() & 0xFFFFFFFF
+    ia, ib = gather_u32(pa, pick), gather_u32(pb, pick)
+    enum_ok = bool(int(e_status.item()) == 0 and
+                   bool(((gather_u32(ea_s, ia) <= gather_u32(b_e, ib)) &
+                         (gather_u32(ea_e, ia) >= gather_u32(b_s, ib))).all().item()))
+    del pairs, pa, pb, index
+    enumeration = {"a_intervals": N_ENUM, "pairs": n_pairs, "index_build_ms": t_index,
+                   "counts_first_offsets_ms": t_ecount, "enumerate_ms": t_enum,
+                   "pairs_per_s": n_pairs / (t_enum / 1e3),
+                   "a_intervals_per_s": N_ENUM / ((t_ecount + t_enum) / 1e3),
+                   "sampled_pairs_valid": enum_ok}
+
     mc_avg = float(np.mean(phase["mc_ms"]))
     mc_evals = N_SHUF * N_MC + N_MC
     achieved = BYTES_PER_EVAL_LEARNED * mc_evals / (mc_avg / 1e3) / 1e9
@@ -273,6 +305,7 @@ def main():
         "mc_shuffles_per_s_plain": N_SHUF / (t_mc_plain / 1e3),
         "learned_equals_plain": bool(agree),
         "rmi": info,
+        "enumeration": enumeration,
         "status": status,
         "roofline": {"bound": "hbm", "kernel": "k_mc<learned> (Monte-Carlo shuffles)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -50,6 +50,8 @@ typedef enum bits_status {
 /* Device status-word bits (OR-ed by kernels). */
 #define BITS_FLAG_INTERVAL 0x1u   /* start > end seen */
 #define BITS_FLAG_CHROM    0x2u   /* interval outside its chromosome */
+#define BITS_FLAG_ENUM     0x4u   /* enumeration: a query's scan found fewer pairs than its
+                                     count, or the pair buffer was too small */
 
 #define BITS_MAX_CHROM   256u     /* chromosomes per genome for projection / Monte-Carlo */
 #define BITS_MAX_DEPTH   13u      /* Eytzinger top-tree levels held in LDS */
@@ -274,6 +276,60 @@ int bits_mc_pvalue(const bits_ref *ref, const uint32_t *d_a_start, const uint32_
 
 /* (1 + n_ge) / (n_shuffles + 1) as one IEEE fp64 division (host). */
 double bits_pvalue(uint64_t n_ge, uint64_t n_shuffles);
+
+/* ---------------------------------------------------------------------- */
+/* Enumeration (Sec. 1.1, sub-problem 4)                                    */
+/* ---------------------------------------------------------------------- */
+
+/* Bytes of an enumeration index over n intervals: uint32 starts[n], ends[n],
+ * ids[n], each region 256-byte aligned (n < 2^32). */
+int bits_enum_index_bytes(uint64_t n, size_t *bytes);
+
+/* Workspace bytes of bits_enum_index_build for n intervals. */
+int bits_enum_index_workspace(uint64_t n, size_t *bytes);
+
+/* Enumeration index: B sorted by start (stable radix sort, so equal starts
+ * keep their input order) with each interval's input index and end moved
+ * along.  d_index is a caller block of bits_enum_index_bytes(n) bytes,
+ * 256-byte aligned; d_b_start / d_b_end are not modified. */
+int bits_enum_index_build(const uint32_t *d_b_start, const uint32_t *d_b_end, uint64_t n, void *d_index,
+                          size_t index_bytes, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes of bits_scan_counts for n counts. */
+int bits_scan_workspace(uint64_t n, size_t *bytes);
+
+/* d_offsets[i] = d_counts[0] + ... + d_counts[i - 1] for i <= n (uint64), so
+ * d_offsets[n] is the total: the output offsets of enumeration. */
+int bits_scan_counts(const uint32_t *d_counts, uint64_t n, uint64_t *d_offsets, void *d_ws, size_t ws_bytes,
+                     void *stream);
+
+/* Step 1 of enumeration in one call: per-query counts (as bits_count_per_query),
+ * d_first[i] = #{B_S <= a_i.end} (the first search of ICount, where the scan
+ * of bits_enumerate starts) and d_offsets = bits_scan_counts(d_counts), so
+ * d_offsets[na] is the number of pairs.  d_ws: bits_scan_workspace(na) bytes. */
+int bits_enum_counts(const bits_ref *ref, const uint32_t *d_a_start, const uint32_t *d_a_end, uint64_t na,
+                     uint32_t *d_counts, uint32_t *d_first, uint64_t *d_offsets, void *d_ws, size_t ws_bytes,
+                     const bits_launch *launch, void *stream);
+
+/* Every intersecting pair (Sec. 1.1): for each query i, the indices b of
+ * the intervals of B that intersect a_i are written to d_pair_b[o .. o + c)
+ * with d_pair_a[.] = i, where o = d_offsets[i] and c = d_counts[i].  Within
+ * a query, pairs come in order of decreasing start of b (equal starts:
+ * decreasing index).  The scan of B sorted by start runs backwards from the
+ * last start <= a_i.end and stops after c hits (Sec. 2.1: the count is the
+ * stop condition); nested intervals cost extra steps.
+ *   d_index     bits_enum_index_build's block for B (n intervals)
+ *   d_counts    bits_count_per_query's (or bits_enum_counts's) counts of the same A
+ *               against the same B
+ *   d_first     bits_enum_counts's d_first, or NULL (then found here by bisection)
+ *   d_offsets   bits_scan_counts of d_counts
+ *   max_pairs   capacity of d_pair_a / d_pair_b; nothing is written at or past it
+ *   d_status    device status word (nullable): BITS_FLAG_ENUM when a scan ends
+ *               short of its count or a pair did not fit, BITS_FLAG_INTERVAL for
+ *               a query with start > end and a non-zero count */
+int bits_enumerate(const void *d_index, uint64_t n, const uint32_t *d_a_start, const uint32_t *d_a_end,
+                   uint64_t na, const uint32_t *d_counts, const uint32_t *d_first, const uint64_t *d_offsets,
+                   uint32_t *d_pair_a, uint32_t *d_pair_b, uint64_t max_pairs, uint32_t *d_status, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Batched pairs: many query sets x many references, one persistent launch  */

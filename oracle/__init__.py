@@ -38,6 +38,9 @@ def lib():
         L.oracle_count_bruteforce.argtypes = [_u32p, _u32p, _c_u64, _u32p, _u32p, _c_u64,
                                               ctypes.c_void_p, ctypes.POINTER(_c_u64)]
         L.oracle_count_bruteforce.restype = None
+        L.oracle_enumerate_bruteforce.argtypes = [_u32p, _u32p, _c_u64, _u32p, _u32p, _c_u64,
+                                                  ctypes.c_void_p, ctypes.c_void_p, _c_u64]
+        L.oracle_enumerate_bruteforce.restype = _c_u64
         L.oracle_count_less.argtypes = [_u32p, _c_u64, _c_u32]
         L.oracle_count_less.restype = _c_u64
         L.oracle_count_le.argtypes = [_u32p, _c_u64, _c_u32]
@@ -111,6 +114,18 @@ def count_bruteforce(a_start, a_end, b_start, b_end):
     lib().oracle_count_bruteforce(a_start, a_end, len(a_start), b_start, b_end, len(b_start),
                                   counts.ctypes.data, ctypes.byref(total))
     return counts, int(total.value)
+
+
+def enumerate_bruteforce(a_start, a_end, b_start, b_end):
+    """Every intersecting pair (i, j) straight from the definition (Sec. 1.1,
+    sub-problem 4), in order of i then j: two uint32 arrays."""
+    a_start, a_end, b_start, b_end = map(_u32, (a_start, a_end, b_start, b_end))
+    f = lib().oracle_enumerate_bruteforce
+    k = int(f(a_start, a_end, len(a_start), b_start, b_end, len(b_start), None, None, 0))
+    pa = np.zeros(max(k, 1), dtype=np.uint32)
+    pb = np.zeros(max(k, 1), dtype=np.uint32)
+    f(a_start, a_end, len(a_start), b_start, b_end, len(b_start), pa.ctypes.data, pb.ctypes.data, k)
+    return pa[:k], pb[:k]
 
 
 def count_less(sorted_arr, x):

@@ -97,6 +97,26 @@ void oracle_count_bruteforce(const uint32_t *as, const uint32_t *ae, uint64_t na
     if (total) *total = t;
 }
 
+/* Enumeration (Sec. 1.1, sub-problem 4) by the same definition: every pair  */
+/* (i, j) with a_i.start <= b_j.end and a_i.end >= b_j.start, in order of i  */
+/* then j.  At most max_pairs pairs are written; returns how many exist.     */
+uint64_t oracle_enumerate_bruteforce(const uint32_t *as, const uint32_t *ae, uint64_t na,
+                                     const uint32_t *bs, const uint32_t *be, uint64_t nb,
+                                     uint32_t *pa, uint32_t *pb, uint64_t max_pairs)
+{
+    uint64_t k = 0;
+    for (uint64_t i = 0; i < na; ++i)
+        for (uint64_t j = 0; j < nb; ++j)
+            if (as[i] <= be[j] && ae[i] >= bs[j]) {
+                if (k < max_pairs) {
+                    pa[k] = (uint32_t)i;
+                    pb[k] = (uint32_t)j;
+                }
+                ++k;
+            }
+    return k;
+}
+
 /* ------------------------------------------------------------------------ */
 /* BSearch (Sec. 2.1).  The equations fix what the two searches return:      */
 /*   last  = |L| = number of sorted ends   strictly below a.start            */

@@ -23,6 +23,7 @@ LIB_PATH = os.environ.get("BITS_LIBRARY") or os.path.join(_HERE, "libbits.so")
 BITS_OK = 0
 BITS_FLAG_INTERVAL = 0x1
 BITS_FLAG_CHROM = 0x2
+BITS_FLAG_ENUM = 0x4
 BITS_MAX_DEPTH = 13
 BITS_PATH_AUTO, BITS_PATH_PLAIN, BITS_PATH_LEARNED = 0, 1, 2
 DEPTH_FROM_REF = 0xFFFFFFFF
@@ -97,6 +98,14 @@ def _load():
                                 ctypes.c_int),
         "bits_rmi_leaf_grad": ([_vp, _vp, _u32, _vp, _vp, _vp, _vp], ctypes.c_int),
         "bits_rmi_window": ([P(bits_ref), _u32, _vp, _u64, _vp, _vp, _vp], ctypes.c_int),
+        "bits_enum_index_bytes": ([_u64, P(_sz)], ctypes.c_int),
+        "bits_enum_index_workspace": ([_u64, P(_sz)], ctypes.c_int),
+        "bits_enum_index_build": ([_vp, _vp, _u64, _vp, _sz, _vp, _sz, _vp], ctypes.c_int),
+        "bits_scan_workspace": ([_u64, P(_sz)], ctypes.c_int),
+        "bits_scan_counts": ([_vp, _u64, _vp, _vp, _sz, _vp], ctypes.c_int),
+        "bits_enum_counts": ([P(bits_ref), _vp, _vp, _u64, _vp, _vp, _vp, _vp, _sz, P(bits_launch), _vp],
+                             ctypes.c_int),
+        "bits_enumerate": ([_vp, _u64, _vp, _vp, _u64, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -487,3 +496,100 @@ def bits_rmi_window(ref: Ref, which: int, x, stream=None):
     _check(_lib.bits_rmi_window(ctypes.byref(ref.c), int(which), _ptr(x), x.numel(), _ptr(lo), _ptr(hi),
                                 _stream(stream)), "bits_rmi_window")
     return lo, hi
+
+
+# ---------------------------------------------------------------- enumeration
+
+@dataclass
+class EnumIndex:
+    """B sorted by start with each interval's end and input index (caller-owned block)."""
+    n: int
+    block: torch.Tensor
+
+    def _region(self, k: int) -> torch.Tensor:
+        stride = (self.n * 4 + 255) // 256 * 256
+        return self.block[k * stride:k * stride + self.n * 4].view(torch.uint32)
+
+    def starts(self) -> torch.Tensor:
+        return self._region(0)
+
+    def ends(self) -> torch.Tensor:
+        return self._region(1)
+
+    def ids(self) -> torch.Tensor:
+        return self._region(2)
+
+
+def bits_enum_index_build(b_start, b_end, stream=None) -> EnumIndex:
+    """Enumeration index over B (stable sort by start; ends and input indices moved along)."""
+    dev = _device()
+    b_start, b_end = _u32_dev(b_start, "b_start"), _u32_dev(b_end, "b_end")
+    n = b_start.numel()
+    if b_end.numel() != n:
+        raise BitsError("b_start and b_end differ in length")
+    nb, nw = _sz(0), _sz(0)
+    _check(_lib.bits_enum_index_bytes(n, ctypes.byref(nb)), "bits_enum_index_bytes")
+    _check(_lib.bits_enum_index_workspace(n, ctypes.byref(nw)), "bits_enum_index_workspace")
+    block = _scratch(nb.value, dev)
+    ws = _scratch(nw.value, dev)
+    _check(_lib.bits_enum_index_build(_ptr(b_start), _ptr(b_end), n, _ptr(block), nb.value, _ptr(ws), nw.value,
+                                      _stream(stream)), "bits_enum_index_build")
+    return EnumIndex(n, block)
+
+
+def bits_scan_counts(counts, stream=None) -> torch.Tensor:
+    """uint64[n + 1] exclusive prefix sums of uint32 counts; the last entry is the total."""
+    dev = _device()
+    counts = _u32_dev(counts, "counts")
+    n = counts.numel()
+    nw = _sz(0)
+    _check(_lib.bits_scan_workspace(n, ctypes.byref(nw)), "bits_scan_workspace")
+    ws = _scratch(nw.value, dev)
+    offsets = torch.empty(n + 1, dtype=torch.uint64, device=dev)
+    _check(_lib.bits_scan_counts(_ptr(counts), n, _ptr(offsets), _ptr(ws), nw.value, _stream(stream)),
+           "bits_scan_counts")
+    return offsets
+
+
+def bits_enum_counts(ref: Ref, a_start, a_end, launch=None, stream=None):
+    """Enumeration step 1: (counts uint32[na], first uint32[na], offsets uint64[na + 1])."""
+    dev = _device()
+    a_start, a_end = _u32_dev(a_start, "a_start"), _u32_dev(a_end, "a_end")
+    na = a_start.numel()
+    if a_end.numel() != na:
+        raise BitsError("a_start and a_end differ in length")
+    counts = torch.empty(na, dtype=torch.uint32, device=dev)
+    first = torch.empty(na, dtype=torch.uint32, device=dev)
+    offsets = torch.empty(na + 1, dtype=torch.uint64, device=dev)
+    nw = _sz(0)
+    _check(_lib.bits_scan_workspace(na, ctypes.byref(nw)), "bits_scan_workspace")
+    ws = _scratch(nw.value, dev)
+    _check(_lib.bits_enum_counts(ctypes.byref(ref.c), _ptr(a_start), _ptr(a_end), na, _ptr(counts), _ptr(first),
+                                 _ptr(offsets), _ptr(ws), nw.value, _lp(launch), _stream(stream)), "bits_enum_counts")
+    return counts, first, offsets
+
+
+def bits_enumerate(index: EnumIndex, a_start, a_end, counts, offsets, first: Optional[torch.Tensor] = None,
+                   max_pairs: Optional[int] = None, status: Optional[torch.Tensor] = None, stream=None):
+    """Every intersecting pair: (pair_a, pair_b) uint32 device tensors of length offsets[-1]
+    (or max_pairs), query i's pairs at [offsets[i], offsets[i] + counts[i]).  `first` from
+    bits_enum_counts saves the kernel its own search."""
+    dev = _device()
+    a_start, a_end = _u32_dev(a_start, "a_start"), _u32_dev(a_end, "a_end")
+    counts = _u32_dev(counts, "counts")
+    na = a_start.numel()
+    if a_end.numel() != na or counts.numel() != na or offsets.numel() != na + 1:
+        raise BitsError("a_start, a_end, counts and offsets disagree in length")
+    if first is not None:
+        first = _u32_dev(first, "first")
+        if first.numel() != na:
+            raise BitsError("first must have one entry per query")
+    if max_pairs is None:
+        max_pairs = int(offsets[-1].item())
+    pa = torch.empty(max(max_pairs, 0), dtype=torch.uint32, device=dev)
+    pb = torch.empty_like(pa)
+    _check(_lib.bits_enumerate(_ptr(index.block) if index.n else ctypes.c_void_p(0), index.n, _ptr(a_start),
+                               _ptr(a_end), na, _ptr(counts), _ptr(first), _ptr(offsets), _ptr(pa), _ptr(pb),
+                               max_pairs,
+                               _ptr(status), _stream(stream)), "bits_enumerate")
+    return pa, pb

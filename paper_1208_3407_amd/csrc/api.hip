@@ -407,6 +407,118 @@ int bits_mc_pvalue(const bits_ref* ref, const uint32_t* d_a_start, const uint32_
     return BITS_OK;
 }
 
+// ---------------------------------------------------------------- enumeration
+
+namespace {
+struct EnumLayout {
+    size_t starts, ends, ids, total;
+};
+EnumLayout enum_layout(uint64_t n) {
+    EnumLayout L;
+    size_t o = 0;
+    L.starts = o; o = align256(o + (size_t)n * sizeof(uint32_t));
+    L.ends = o; o = align256(o + (size_t)n * sizeof(uint32_t));
+    L.ids = o; o = align256(o + (size_t)n * sizeof(uint32_t));
+    L.total = o;
+    return L;
+}
+}  // namespace
+
+int bits_enum_index_bytes(uint64_t n, size_t* bytes) {
+    if (!bytes || n > 0xFFFFFFFFull) return BITS_E_ARG;
+    *bytes = enum_layout(n).total;
+    return BITS_OK;
+}
+
+int bits_enum_index_workspace(uint64_t n, size_t* bytes) {
+    if (!bytes || n > 0xFFFFFFFFull) return BITS_E_ARG;
+    const uint32_t vm = 2;
+    *bytes = sort_workspace_bytes(&n, 1, &vm);
+    return BITS_OK;
+}
+
+int bits_enum_index_build(const uint32_t* d_b_start, const uint32_t* d_b_end, uint64_t n, void* d_index,
+                          size_t index_bytes, void* d_ws, size_t ws_bytes, void* stream) {
+    if (n > 0xFFFFFFFFull || !d_index || ((uintptr_t)d_index & 255u)) return BITS_E_ARG;
+    if (n && (!d_b_start || !d_b_end || !d_ws)) return BITS_E_ARG;
+    const EnumLayout L = enum_layout(n);
+    if (index_bytes < L.total) return BITS_E_WORKSPACE;
+    if (!n) return BITS_OK;
+    size_t need = 0;
+    bits_enum_index_workspace(n, &need);
+    if (ws_bytes < need) return BITS_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char* b = (char*)d_index;
+    uint32_t* starts = (uint32_t*)(b + L.starts);
+    uint32_t* ends = (uint32_t*)(b + L.ends);
+    uint32_t* ids = (uint32_t*)(b + L.ids);
+    SortSeg seg{d_b_start, starts, n, 2u, nullptr, ids};
+    const int rc = launch_sort(&seg, 1, d_ws, ws_bytes, s);
+    if (rc != BITS_OK) return rc;
+    BITS_CHECK_HIP(launch_gather_u32(d_b_end, ids, n, ends, s));
+    return BITS_OK;
+}
+
+int bits_scan_workspace(uint64_t n, size_t* bytes) {
+    if (!bytes) return BITS_E_ARG;
+    *bytes = align256((size_t)std::max<uint64_t>(scan_tiles(n), 1) * sizeof(uint64_t));
+    return BITS_OK;
+}
+
+int bits_scan_counts(const uint32_t* d_counts, uint64_t n, uint64_t* d_offsets, void* d_ws, size_t ws_bytes,
+                     void* stream) {
+    if (!d_offsets || (n && (!d_counts || !d_ws))) return BITS_E_ARG;
+    size_t need = 0;
+    bits_scan_workspace(n, &need);
+    if (n && ws_bytes < need) return BITS_E_WORKSPACE;
+    BITS_CHECK_HIP(launch_scan_counts(d_counts, n, d_offsets, (uint64_t*)d_ws, (hipStream_t)stream));
+    return BITS_OK;
+}
+
+int bits_enum_counts(const bits_ref* ref, const uint32_t* d_a_start, const uint32_t* d_a_end, uint64_t na,
+                     uint32_t* d_counts, uint32_t* d_first, uint64_t* d_offsets, void* d_ws, size_t ws_bytes,
+                     const bits_launch* launch, void* stream) {
+    int rc = check_queries(ref, d_a_start, d_a_end, na);
+    if (rc != BITS_OK) return rc;
+    if (na > 0xFFFFFFFFull || !d_offsets || (na && (!d_counts || !d_first))) return BITS_E_ARG;
+    size_t need = 0;
+    bits_scan_workspace(na, &need);
+    if (na && (!d_ws || ws_bytes < need)) return BITS_E_WORKSPACE;
+    LaunchCfg cfg;
+    rc = resolve_launch(ref, launch, &cfg);
+    if (rc != BITS_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (na) {
+        if (ref->n) {
+            BITS_CHECK_HIP(launch_count(make_search_args(ref, cfg), cfg, d_a_start, d_a_end, na, d_counts, nullptr, s,
+                                        d_first));
+        } else {
+            BITS_CHECK_HIP(launch_fill_u32(d_counts, na, 0u, s));
+            BITS_CHECK_HIP(launch_fill_u32(d_first, na, 0u, s));
+        }
+    }
+    BITS_CHECK_HIP(launch_scan_counts(d_counts, na, d_offsets, (uint64_t*)d_ws, s));
+    return BITS_OK;
+}
+
+int bits_enumerate(const void* d_index, uint64_t n, const uint32_t* d_a_start, const uint32_t* d_a_end,
+                   uint64_t na, const uint32_t* d_counts, const uint32_t* d_first, const uint64_t* d_offsets,
+                   uint32_t* d_pair_a, uint32_t* d_pair_b, uint64_t max_pairs, uint32_t* d_status, void* stream) {
+    if (n > 0xFFFFFFFFull || na > 0xFFFFFFFFull) return BITS_E_ARG;
+    if (!na) return BITS_OK;
+    if (!d_a_start || !d_a_end || !d_counts || !d_offsets) return BITS_E_ARG;
+    if (max_pairs && (!d_pair_a || !d_pair_b)) return BITS_E_ARG;
+    if (n && (!d_index || ((uintptr_t)d_index & 255u))) return BITS_E_ARG;
+    if (!n) return BITS_OK;   // every count is 0
+    const EnumLayout L = enum_layout(n);
+    const char* b = (const char*)d_index;
+    BITS_CHECK_HIP(launch_enumerate((const uint32_t*)(b + L.starts), (const uint32_t*)(b + L.ends),
+                                    (const uint32_t*)(b + L.ids), (uint32_t)n, d_a_start, d_a_end, na, d_counts,
+                                    d_first, d_offsets, d_pair_a, d_pair_b, max_pairs, d_status,
+                                    (hipStream_t)stream));
+    return BITS_OK;
+}
+
 double bits_pvalue(uint64_t n_ge, uint64_t n_shuffles) {
     return (1.0 + (double)n_ge) / ((double)n_shuffles + 1.0);
 }

@@ -169,8 +169,10 @@ SearchArgs make_search_args(const bits_ref* ref, const LaunchCfg& cfg);
 // search.hip
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+// counts (nullable), firsts (nullable: #{B_S <= a.end} per query), total (nullable)
 hipError_t launch_count(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
-                        uint64_t na, uint32_t* counts, unsigned long long* total, hipStream_t s);
+                        uint64_t na, uint32_t* counts, unsigned long long* total, hipStream_t s,
+                        uint32_t* firsts = nullptr);
 // Monte-Carlo query table in the caller's workspace: uint32[na] each of
 // chromosome offset, legal-start count, length and original index, grouped
 // by chromosome; hist and cursor hold BITS_MAX_CHROM words each.
@@ -211,17 +213,32 @@ hipError_t launch_batch(const BatchRef* refs, const BatchQuery* qs, const BatchI
                         hipStream_t s);
 
 // sort.hip
+// One segment to sort: n keys in -> out, optionally with one uint32 value per
+// key moved along (vmode 1: values from vin; 2: the input index 0..n-1).
 struct SortSeg {
     const uint32_t* in;
     uint32_t* out;
     uint64_t n;
+    uint32_t vmode = 0;
+    const uint32_t* vin = nullptr;
+    uint32_t* vout = nullptr;
 };
-size_t sort_workspace_bytes(const uint64_t* n, uint32_t nseg);
+size_t sort_workspace_bytes(const uint64_t* n, uint32_t nseg, const uint32_t* vmode = nullptr);
 int launch_sort(const SortSeg* segs, uint32_t nseg, void* ws, size_t ws_bytes, hipStream_t s);
 hipError_t launch_build_tree(const uint32_t* keys, uint64_t n, uint32_t depth, uint32_t* tree, hipStream_t s);
 // Line heads of a sorted array: H[j] = keys[32 j] for j < ceil(n / 32), then
 // 0xFFFFFFFF up to heads_len(n) entries.
 hipError_t launch_build_heads(const uint32_t* keys, uint64_t n, uint32_t* heads, hipStream_t s);
+
+// enum.hip
+uint64_t scan_tiles(uint64_t n);
+hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* idx, uint64_t n, uint32_t* dst, hipStream_t s);
+hipError_t launch_scan_counts(const uint32_t* counts, uint64_t n, uint64_t* offsets, uint64_t* tile_sum,
+                              hipStream_t s);
+hipError_t launch_enumerate(const uint32_t* starts, const uint32_t* ends, const uint32_t* ids, uint32_t n,
+                            const uint32_t* as, const uint32_t* ae, uint64_t na, const uint32_t* counts,
+                            const uint32_t* firsts, const uint64_t* offsets, uint32_t* pa, uint32_t* pb,
+                            uint64_t max_pairs, uint32_t* status, hipStream_t s);
 
 // rmi.hip
 size_t rmi_workspace_bytes();

@@ -271,7 +271,8 @@ constexpr uint32_t kPlainHotSteps = 3;
 template <int QPL>
 __device__ __forceinline__ void icount_plain(const SearchArgs& sa, const uint32_t* lds,
                                              const uint32_t (&as)[QPL], const uint32_t (&ae)[QPL],
-                                             uint32_t (&cnt)[QPL]) {
+                                             uint32_t (&cnt)[QPL],
+                                             uint32_t (&fst)[QPL]) {
     constexpr int NC = 2 * QPL;
     uint32_t x[NC], base[NC], len[NC];
 #pragma unroll
@@ -307,6 +308,7 @@ __device__ __forceinline__ void icount_plain(const SearchArgs& sa, const uint32_
     for (int q = 0; q < QPL; ++q) {
         const uint32_t first = (ae[q] == 0xFFFFFFFFu) ? sa.n : base[2 * q];
         cnt[q] = first - base[2 * q + 1];
+        fst[q] = first;
     }
 }
 
@@ -377,7 +379,8 @@ __device__ __forceinline__ void learned_windows(const SearchArgs& sa, uint32_t* 
 
 template <int QPL>
 __device__ __forceinline__ void icount_learned(const SearchArgs& sa, uint32_t* scr, const uint32_t (&as)[QPL],
-                                               const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL]) {
+                                               const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL],
+                                               uint32_t (&fst)[QPL]) {
     constexpr int NC = 2 * QPL;
     uint32_t x[NC], base[NC], len[NC], wl[NC], wr[NC], rlo[NC], rhi[NC], ln[NC], pc[NC];
     bool win[NC];
@@ -443,6 +446,7 @@ __device__ __forceinline__ void icount_learned(const SearchArgs& sa, uint32_t* s
     for (int q = 0; q < QPL; ++q) {
         const uint32_t first = (ae[q] == 0xFFFFFFFFu) ? sa.n : base[2 * q];
         cnt[q] = first - base[2 * q + 1];
+        fst[q] = first;
     }
 }
 
@@ -492,7 +496,8 @@ __device__ __forceinline__ uint32_t head_outcome(uint32_t w, uint32_t cnt) {
 
 template <int QPL>
 __device__ __forceinline__ void icount_heads(const SearchArgs& sa, uint32_t* scr, const uint32_t (&as)[QPL],
-                                             const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL]) {
+                                             const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL],
+                                             uint32_t (&fst)[QPL]) {
     constexpr int NC = 2 * QPL;
     uint32_t x[NC], rlo[NC], rhi[NC], pred[NC], err[NC], w[NC], pc[NC], st[NC];
     bool inside[NC];
@@ -565,16 +570,17 @@ __device__ __forceinline__ void icount_heads(const SearchArgs& sa, uint32_t* scr
     for (int q = 0; q < QPL; ++q) {
         const uint32_t first = (ae[q] == 0xFFFFFFFFu) ? sa.n : r[2 * q];
         cnt[q] = first - r[2 * q + 1];
+        fst[q] = first;
     }
 }
 
 template <int QPL, bool LEARNED>
 __device__ __forceinline__ void icount(const SearchArgs& sa, uint32_t* lds, const uint32_t (&as)[QPL],
-                                       const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL]) {
+                                       const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL], uint32_t (&fst)[QPL]) {
     if constexpr (LEARNED)
-        icount_learned<QPL>(sa, lds + (threadIdx.x / kWave) * probe_scratch_words(QPL), as, ae, cnt);
+        icount_learned<QPL>(sa, lds + (threadIdx.x / kWave) * probe_scratch_words(QPL), as, ae, cnt, fst);
     else
-        icount_plain<QPL>(sa, lds, as, ae, cnt);
+        icount_plain<QPL>(sa, lds, as, ae, cnt, fst);
 }
 
 
@@ -586,7 +592,8 @@ __device__ __forceinline__ void icount(const SearchArgs& sa, uint32_t* lds, cons
 template <int QPL, bool LEARNED>
 BITS_SEARCH_KERNEL k_count(SearchArgs sa, const uint32_t* __restrict__ a_start,
                                                 const uint32_t* __restrict__ a_end, uint64_t na,
-                                                uint32_t* __restrict__ counts, unsigned long long* total) {
+                                                uint32_t* __restrict__ counts, uint32_t* __restrict__ firsts,
+                                                unsigned long long* total) {
     extern __shared__ uint32_t lds[];
     if (!LEARNED) {
         stage_tree(lds, sa.tree, sa.tree_stride, sa.depth);
@@ -611,12 +618,14 @@ BITS_SEARCH_KERNEL k_count(SearchArgs sa, const uint32_t* __restrict__ a_start,
                 ae[q] = as[q];
             }
         }
-        icount<QPL, LEARNED>(sa, lds, as, ae, cnt);
+        uint32_t fst[QPL];
+        icount<QPL, LEARNED>(sa, lds, as, ae, cnt, fst);
 #pragma unroll
         for (int q = 0; q < QPL; ++q) {
             const uint64_t i = t * tile + (uint64_t)q * blockDim.x + threadIdx.x;
             const uint32_t c = valid[q] ? cnt[q] : 0u;
             if (counts && i < na) counts[i] = c;
+            if (firsts && i < na) firsts[i] = fst[q];
             acc += c;
         }
     }
@@ -652,10 +661,11 @@ constexpr uint32_t kXcds = 8;
 template <int QPL, bool LEARNED>
 __device__ __forceinline__ void icount_mc(const SearchArgs& sa, uint32_t* lds, const uint32_t (&as)[QPL],
                                           const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL]) {
+    uint32_t fst[QPL];
     if constexpr (LEARNED)
-        icount_heads<QPL>(sa, lds + (threadIdx.x / kWave) * probe_scratch_words(QPL), as, ae, cnt);
+        icount_heads<QPL>(sa, lds + (threadIdx.x / kWave) * probe_scratch_words(QPL), as, ae, cnt, fst);
     else
-        icount_plain<QPL>(sa, lds, as, ae, cnt);
+        icount_plain<QPL>(sa, lds, as, ae, cnt, fst);
 }
 
 template <int QPL, bool LEARNED, bool OBSERVED>
@@ -915,7 +925,8 @@ __global__ void __launch_bounds__(1024)
             }
         }
         if (sa.n) {
-            icount_plain<QPL>(sa, lds, as, ae, cnt);
+            uint32_t fst[QPL];
+            icount_plain<QPL>(sa, lds, as, ae, cnt, fst);
         } else {
 #pragma unroll
             for (int q = 0; q < QPL; ++q) cnt[q] = 0;
@@ -1042,26 +1053,28 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
 
 template <int QPL, bool LEARNED>
 static hipError_t launch_count_t(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
-                                 uint64_t na, uint32_t* counts, unsigned long long* total, hipStream_t s) {
+                                 uint64_t na, uint32_t* counts, uint32_t* firsts, unsigned long long* total,
+                                 hipStream_t s) {
     const size_t lds = search_lds_bytes(LEARNED, sa.depth, QPL, cfg.block);
     const uint64_t tile = (uint64_t)cfg.block * QPL;
     const void* kern = (const void*)k_count<QPL, LEARNED>;
     const uint32_t grid = persistent_grid(kern, cfg, lds, (na + tile - 1) / tile);
-    hipLaunchKernelGGL((k_count<QPL, LEARNED>), dim3(grid), dim3(cfg.block), lds, s, sa, as, ae, na, counts, total);
+    hipLaunchKernelGGL((k_count<QPL, LEARNED>), dim3(grid), dim3(cfg.block), lds, s, sa, as, ae, na, counts, firsts,
+                       total);
     return hipGetLastError();
 }
 
 hipError_t launch_count(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
-                        uint64_t na, uint32_t* counts, unsigned long long* total, hipStream_t s) {
+                        uint64_t na, uint32_t* counts, unsigned long long* total, hipStream_t s, uint32_t* firsts) {
     if (!na) return hipSuccess;
     const bool L = cfg.path == BITS_PATH_LEARNED;
     switch (cfg.qpl) {
-        case 1: return L ? launch_count_t<1, true>(sa, cfg, as, ae, na, counts, total, s)
-                         : launch_count_t<1, false>(sa, cfg, as, ae, na, counts, total, s);
-        case 4: return L ? launch_count_t<4, true>(sa, cfg, as, ae, na, counts, total, s)
-                         : launch_count_t<4, false>(sa, cfg, as, ae, na, counts, total, s);
-        default: return L ? launch_count_t<2, true>(sa, cfg, as, ae, na, counts, total, s)
-                          : launch_count_t<2, false>(sa, cfg, as, ae, na, counts, total, s);
+        case 1: return L ? launch_count_t<1, true>(sa, cfg, as, ae, na, counts, firsts, total, s)
+                         : launch_count_t<1, false>(sa, cfg, as, ae, na, counts, firsts, total, s);
+        case 4: return L ? launch_count_t<4, true>(sa, cfg, as, ae, na, counts, firsts, total, s)
+                         : launch_count_t<4, false>(sa, cfg, as, ae, na, counts, firsts, total, s);
+        default: return L ? launch_count_t<2, true>(sa, cfg, as, ae, na, counts, firsts, total, s)
+                          : launch_count_t<2, false>(sa, cfg, as, ae, na, counts, firsts, total, s);
     }
 }
 

@@ -1,8 +1,10 @@
 // On-device LSD radix sort of uint32 keys (the two Sort steps of Algorithm 2)
 // and the Eytzinger top-tree build.
 //
-// Segmented and keys-only: every segment (e.g. B_S and B_E of one or many
-// references) is sorted independently in the same launches.  Four passes of
+// Segmented: every segment (e.g. B_S and B_E of one or many references) is
+// sorted independently in the same launches, keys only or with one uint32
+// value per key carried along (explicit, or the implicit 0..n-1 input order;
+// the sort is stable, so equal keys keep their input order).  Four passes of
 // 8-bit digits, reduce-then-scan per pass:
 //   tile histogram -> per (segment, digit) scan over tiles -> stable scatter.
 // A digit that is constant over every segment is skipped (decided on the
@@ -29,8 +31,13 @@ struct SegDesc {
     uint32_t* out;
     uint32_t n;
     uint32_t tile0;   // first global tile of the segment
+    const uint32_t* vin;   // values: input (nullptr with vmode 2: the input index)
+    uint32_t* vping;
+    uint32_t* vout;
+    uint32_t vmode;   // 0 keys only, 1 values from vin, 2 values = input index
+    uint32_t pad;
 };
-static_assert(sizeof(SegDesc) == 32, "SegDesc layout");
+static_assert(sizeof(SegDesc) == 64, "SegDesc layout");
 
 struct SortPlan {
     uint32_t active[4];
@@ -40,7 +47,7 @@ struct SortPlan {
     uint32_t pad[3];
 };
 
-constexpr int kDescChunk = 96;
+constexpr int kDescChunk = 48;   // 3 KB of kernel arguments
 struct DescChunk {
     SegDesc d[kDescChunk];
 };
@@ -59,6 +66,12 @@ __device__ __forceinline__ const uint32_t* buf_ro(const SegDesc& d, uint32_t sel
 }
 __device__ __forceinline__ uint32_t* buf_rw(const SegDesc& d, uint32_t sel) {
     return sel == 1 ? d.ping : d.out;
+}
+__device__ __forceinline__ const uint32_t* vbuf_ro(const SegDesc& d, uint32_t sel) {
+    return sel == 0 ? d.vin : sel == 1 ? d.vping : d.vout;
+}
+__device__ __forceinline__ uint32_t* vbuf_rw(const SegDesc& d, uint32_t sel) {
+    return sel == 1 ? d.vping : d.vout;
 }
 
 // Exclusive scan of one value per thread over a 256-thread block.
@@ -217,12 +230,14 @@ __global__ void __launch_bounds__(kThreads) k_tile_scan(const SegDesc* __restric
 // tile in 16 rounds; within a round, lanes holding the same digit are found
 // with 8 ballots and ranked by lane order.  The tile is then sorted by digit
 // in LDS and written out in digit runs (coalesced).
+template <bool VALS>
 __global__ void __launch_bounds__(kThreads) k_scatter(const SegDesc* __restrict__ descs, uint32_t nseg,
                                                       const SortPlan* __restrict__ plan, int p, uint32_t ntiles,
                                                       const uint32_t* __restrict__ H,
                                                       const uint32_t* __restrict__ seg_pre) {
     if (!plan->active[p]) return;
     __shared__ uint32_t keys_lds[kTile];
+    __shared__ uint32_t vals_lds[VALS ? kTile : 1];
     __shared__ uint32_t wcnt[kWaves][256];
     __shared__ uint32_t dstart[256];
     __shared__ uint32_t goff[256];
@@ -234,6 +249,11 @@ __global__ void __launch_bounds__(kThreads) k_scatter(const SegDesc* __restrict_
     const uint32_t cnt = min(kTile, d.n - begin);
     const uint32_t* src = buf_ro(d, plan->src[p]) + begin;
     uint32_t* dst = buf_rw(d, plan->dst[p]);
+    // values: vmode 2 reads the input index on the first active pass
+    const bool vals = VALS && d.vmode != 0;
+    const bool iota = d.vmode == 2 && plan->src[p] == 0;
+    const uint32_t* vsrc = vals && !iota ? vbuf_ro(d, plan->src[p]) + begin : nullptr;
+    uint32_t* vdst = vals ? vbuf_rw(d, plan->dst[p]) : nullptr;
     const uint32_t shift = 8u * p;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -285,14 +305,22 @@ __global__ void __launch_bounds__(kThreads) k_scatter(const SegDesc* __restrict_
         const uint32_t idx = (uint32_t)w * kPerWave + (uint32_t)r * kWave + lane;
         if (idx < cnt) {
             const uint32_t dg = (key[r] >> shift) & 255u;
-            keys_lds[dstart[dg] + wcnt[w][dg] + rank[r]] = key[r];
+            const uint32_t at = dstart[dg] + wcnt[w][dg] + rank[r];
+            keys_lds[at] = key[r];
+            if constexpr (VALS) {
+                if (vals) vals_lds[at] = iota ? begin + idx : vsrc[idx];
+            }
         }
     }
     __syncthreads();
     for (uint32_t k = threadIdx.x; k < cnt; k += kThreads) {
         const uint32_t v = keys_lds[k];
         const uint32_t dg = (v >> shift) & 255u;
-        dst[goff[dg] + (k - dstart[dg])] = v;
+        const uint32_t at = goff[dg] + (k - dstart[dg]);
+        dst[at] = v;
+        if constexpr (VALS) {
+            if (vals) vdst[at] = vals_lds[k];
+        }
     }
 }
 
@@ -304,7 +332,10 @@ __global__ void k_copy_if_idle(const SegDesc* __restrict__ descs, uint32_t nseg,
     const SegDesc d = descs[s];
     const uint32_t begin = (t - d.tile0) * kTile;
     const uint32_t cnt = min(kTile, d.n - begin);
-    for (uint32_t k = threadIdx.x; k < cnt; k += kThreads) d.out[begin + k] = d.in[begin + k];
+    for (uint32_t k = threadIdx.x; k < cnt; k += kThreads) {
+        d.out[begin + k] = d.in[begin + k];
+        if (d.vmode) d.vout[begin + k] = d.vmode == 2 ? begin + k : d.vin[begin + k];
+    }
 }
 
 // Eytzinger top tree: node k (level l = floor(log2 k), j = k - 2^l) holds
@@ -333,16 +364,17 @@ __global__ void k_build_heads(const uint32_t* __restrict__ keys, uint64_t n, uin
 }
 
 struct WsLayout {
-    size_t descs, plan, seg_hist, seg_pre, H, ping, total;
+    size_t descs, plan, seg_hist, seg_pre, H, ping, vping, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static WsLayout ws_layout(const uint64_t* n, uint32_t nseg) {
-    uint64_t ntiles = 0, nkeys = 0;
+static WsLayout ws_layout(const uint64_t* n, uint32_t nseg, const uint32_t* vmode) {
+    uint64_t ntiles = 0, nkeys = 0, nvals = 0;
     for (uint32_t s = 0; s < nseg; ++s) {
         ntiles += (n[s] + kTile - 1) / kTile;
         nkeys += n[s];
+        if (vmode && vmode[s]) nvals += n[s];
     }
     WsLayout L;
     size_t o = 0;
@@ -352,21 +384,29 @@ static WsLayout ws_layout(const uint64_t* n, uint32_t nseg) {
     L.seg_pre = o; o = align256(o + (size_t)nseg * 1024 * 4);
     L.H = o; o = align256(o + (size_t)ntiles * 256 * 4);
     L.ping = o; o = align256(o + (size_t)nkeys * 4);
+    L.vping = o; o = align256(o + (size_t)nvals * 4);
     L.total = o;
     return L;
 }
 
 }  // namespace
 
-size_t sort_workspace_bytes(const uint64_t* n, uint32_t nseg) { return ws_layout(n, nseg).total; }
+size_t sort_workspace_bytes(const uint64_t* n, uint32_t nseg, const uint32_t* vmode) {
+    return ws_layout(n, nseg, vmode).total;
+}
 
 int launch_sort(const SortSeg* segs, uint32_t nseg, void* ws, size_t ws_bytes, hipStream_t s) {
     std::vector<uint64_t> ns(nseg);
+    std::vector<uint32_t> vm(nseg);
     for (uint32_t i = 0; i < nseg; ++i) {
-        if (segs[i].n > 0xFFFFFFFFull) return BITS_E_ARG;
+        if (segs[i].n > 0xFFFFFFFFull || segs[i].vmode > 2) return BITS_E_ARG;
+        if ((segs[i].vmode == 1 && !segs[i].vin) || (segs[i].vmode && !segs[i].vout)) return BITS_E_ARG;
         ns[i] = segs[i].n;
+        vm[i] = segs[i].vmode;
     }
-    const WsLayout L = ws_layout(ns.data(), nseg);
+    const WsLayout L = ws_layout(ns.data(), nseg, vm.data());
+    bool any_vals = false;
+    for (uint32_t i = 0; i < nseg; ++i) any_vals |= vm[i] != 0;
     if (ws_bytes < L.total) return BITS_E_WORKSPACE;
     char* base = (char*)ws;
     SegDesc* descs = (SegDesc*)(base + L.descs);
@@ -375,11 +415,12 @@ int launch_sort(const SortSeg* segs, uint32_t nseg, void* ws, size_t ws_bytes, h
     uint32_t* seg_pre = (uint32_t*)(base + L.seg_pre);
     uint32_t* H = (uint32_t*)(base + L.H);
     uint32_t* ping = (uint32_t*)(base + L.ping);
+    uint32_t* vping = (uint32_t*)(base + L.vping);
 
     // Descriptors, written by small kernels from by-value chunks so the call
     // stays asynchronous and capturable.
     uint32_t tile0 = 0;
-    uint64_t koff = 0;
+    uint64_t koff = 0, voff = 0;
     for (uint32_t c0 = 0; c0 < nseg; c0 += kDescChunk) {
         DescChunk ch;
         memset(&ch, 0, sizeof(ch));
@@ -391,6 +432,13 @@ int launch_sort(const SortSeg* segs, uint32_t nseg, void* ws, size_t ws_bytes, h
             ch.d[i].ping = ping + koff;
             ch.d[i].n = (uint32_t)g.n;
             ch.d[i].tile0 = tile0;
+            ch.d[i].vmode = g.vmode;
+            if (g.vmode) {
+                ch.d[i].vin = g.vmode == 1 ? g.vin : nullptr;
+                ch.d[i].vping = vping + voff;
+                ch.d[i].vout = g.vout;
+                voff += g.n;
+            }
             tile0 += (uint32_t)((g.n + kTile - 1) / kTile);
             koff += g.n;
         }
@@ -411,7 +459,12 @@ int launch_sort(const SortSeg* segs, uint32_t nseg, void* ws, size_t ws_bytes, h
     for (int p = 0; p < 4; ++p) {
         hipLaunchKernelGGL(k_tile_hist, dim3(ntiles), dim3(kThreads), 0, s, descs, nseg, plan, p, ntiles, H);
         hipLaunchKernelGGL(k_tile_scan, dim3(nseg * 256), dim3(kThreads), 0, s, descs, plan, p, ntiles, H);
-        hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(kThreads), 0, s, descs, nseg, plan, p, ntiles, H, seg_pre);
+        if (any_vals)
+            hipLaunchKernelGGL(k_scatter<true>, dim3(ntiles), dim3(kThreads), 0, s, descs, nseg, plan, p, ntiles, H,
+                               seg_pre);
+        else
+            hipLaunchKernelGGL(k_scatter<false>, dim3(ntiles), dim3(kThreads), 0, s, descs, nseg, plan, p, ntiles, H,
+                               seg_pre);
     }
     hipLaunchKernelGGL(k_copy_if_idle, dim3(ntiles), dim3(kThreads), 0, s, descs, nseg, plan);
     BITS_CHECK_HIP(hipGetLastError());

@@ -400,3 +400,31 @@ def test_linear_fit_vs_polyfit():
     a, b = oracle.linear_fit(x)
     pa, pb = np.polyfit(x.astype(np.float64), np.arange(len(x), dtype=np.float64), 1)
     assert abs(a - pa) <= 1e-9 * abs(pa) and abs(b - pb) <= 1e-6 * max(1.0, abs(pb))
+
+
+def test_enumeration_oracle_golden(enum_golden):
+    """Sub-problem 4 by the definition reproduces the hand-derived pair sets of
+    a nested, tied fixture."""
+    B, Q = enum_golden
+    b = np.array(B, dtype=np.uint32)
+    a = np.array([(s, e) for s, e, _, _ in Q], dtype=np.uint32)
+    pa, pb = oracle.enumerate_bruteforce(a[:, 0], a[:, 1], b[:, 0], b[:, 1])
+    for i, (_, _, st, _) in enumerate(Q):
+        assert list(pb[pa == i]) == st, i
+
+
+def test_enumeration_oracle_random():
+    """Per query: every pair satisfies the closed predicate, none repeats, and
+    the number of pairs equals the library-routine count (numpy searchsorted);
+    the number of all pairs equals the independent endpoint sweep."""
+    r = np.random.default_rng(42)
+    for na, nb, span, ml in ((300, 500, 5_000, 60), (200, 2_000, 100_000, 3_000), (50, 40, 30, 0)):
+        b_s = r.integers(0, span, nb).astype(np.uint32)
+        b_e = b_s + r.integers(0, ml + 1, nb).astype(np.uint32)
+        a_s = r.integers(0, span, na).astype(np.uint32)
+        a_e = a_s + r.integers(0, ml + 1, na).astype(np.uint32)
+        pa, pb = oracle.enumerate_bruteforce(a_s, a_e, b_s, b_e)
+        assert np.all((a_s[pa] <= b_e[pb]) & (a_e[pa] >= b_s[pb]))
+        assert len(np.unique(pa.astype(np.uint64) * nb + pb)) == len(pa)
+        assert np.array_equal(np.bincount(pa, minlength=na), _np_count(a_s, a_e, b_s, b_e))
+        assert len(pa) == oracle.sweep_total(a_s, a_e, b_s, b_e)
