@@ -276,6 +276,18 @@ def main():
                    "a_intervals_per_s": N_ENUM / ((t_ecount + t_enum) / 1e3),
                    "sampled_pairs_valid": enum_ok}
 
+    # significance summary of the timed Monte-Carlo run (Sec. 3.2, Sec. 3.3) and the decision sub-problem
+    m_lo, m_hi = bits.bits_mc_median(mc_out.totals)
+    m_lo, m_hi = int(m_lo.item()), int(m_hi.item())
+    obs, n_ge, n_le = int(mc_out.observed.item()), int(mc_out.n_ge.item()), int(mc_out.n_le.item())
+    significance = {"observed": obs, "median": (m_lo + m_hi) / 2, "enrichment_log2": bits.bits_enrichment(obs, m_lo, m_hi),
+                    "n_ge": n_ge, "n_le": n_le, "p_upper": bits.bits_pvalue(n_ge, N_SHUF),
+                    "p_lower": bits.bits_pvalue_lower(n_le, N_SHUF),
+                    "p_two_sided": bits.bits_pvalue_two_sided(n_ge, n_le, N_SHUF)}
+    t_decide = timed(lambda: bits.bits_decide(ref, a_s, a_e, launch=lp_learned))
+    significance["decide_ms"] = t_decide
+    significance["decide_found"] = int(bits.bits_decide(ref, a_s, a_e, launch=lp_learned)[0].item())
+
     mc_avg = float(np.mean(phase["mc_ms"]))
     mc_evals = N_SHUF * N_MC + N_MC
     achieved = BYTES_PER_EVAL_LEARNED * mc_evals / (mc_avg / 1e3) / 1e9
@@ -306,6 +318,7 @@ def main():
         "learned_equals_plain": bool(agree),
         "rmi": info,
         "enumeration": enumeration,
+        "significance": significance,
         "status": status,
         "roofline": {"bound": "hbm", "kernel": "k_mc<learned> (Monte-Carlo shuffles)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -241,6 +241,15 @@ int bits_count_per_query(const bits_ref *ref, const uint32_t *d_a_start, const u
 int bits_count(const bits_ref *ref, const uint32_t *d_a_start, const uint32_t *d_a_end,
                uint64_t na, uint64_t *d_total, const bits_launch *launch, void *stream);
 
+/* Decision (Sec. 1.1, sub-problem 1): *d_found = 1 if some a_i intersects
+ * some interval of B, else 0.  Workgroups stop taking tiles of A once a hit
+ * is seen.  *d_witness = an index i with count_i > 0 (the smallest among the
+ * tiles that ran, so not necessarily the smallest overall), or 2^64 - 1.  A
+ * query with start > end sets BITS_FLAG_INTERVAL in ref->status and is
+ * skipped. */
+int bits_decide(const bits_ref *ref, const uint32_t *d_a_start, const uint32_t *d_a_end, uint64_t na,
+                uint32_t *d_found, uint64_t *d_witness, const bits_launch *launch, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Monte-Carlo significance (Sec. 3.2)                                      */
 /* ---------------------------------------------------------------------- */
@@ -276,6 +285,23 @@ int bits_mc_pvalue(const bits_ref *ref, const uint32_t *d_a_start, const uint32_
 
 /* (1 + n_ge) / (n_shuffles + 1) as one IEEE fp64 division (host). */
 double bits_pvalue(uint64_t n_ge, uint64_t n_shuffles);
+
+/* Lower tail (depletion): (1 + n_le) / (n_shuffles + 1) (host). */
+double bits_pvalue_lower(uint64_t n_le, uint64_t n_shuffles);
+
+/* Two-sided: min(1, 2 min(upper, lower)) of the two one-sided values (host). */
+double bits_pvalue_two_sided(uint64_t n_ge, uint64_t n_le, uint64_t n_shuffles);
+
+/* Median of the per-shuffle totals (Sec. 3.3, Fig. 3): *d_lo = the
+ * floor((n-1)/2)-th and *d_hi = the floor(n/2)-th smallest of d_totals[0..n)
+ * (0-based; equal when n is odd), exact, by radix selection on the device.
+ * The median is (lo + hi) / 2.  1 <= n < 2^32. */
+int bits_mc_median(const uint64_t *d_totals, uint64_t n, uint64_t *d_lo, uint64_t *d_hi, void *stream);
+
+/* Enrichment score of Sec. 3.3 / Fig. 3: log2(observed / median) with
+ * median = (lo + hi) / 2, in IEEE fp64 on the host (an observed count of 0
+ * gives -inf; a median of 0 gives +inf, or NaN when observed is 0 too). */
+double bits_enrichment(uint64_t observed, uint64_t median_lo, uint64_t median_hi);
 
 /* ---------------------------------------------------------------------- */
 /* Enumeration (Sec. 1.1, sub-problem 4)                                    */

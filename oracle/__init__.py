@@ -61,6 +61,8 @@ def lib():
         L.oracle_mc_tail.argtypes = [_u64p, _c_u64, _c_u64, ctypes.POINTER(_c_u64),
                                      ctypes.POINTER(_c_u64)]
         L.oracle_mc_tail.restype = None
+        L.oracle_mc_median.argtypes = [_u64p, _c_u64, ctypes.POINTER(_c_u64), ctypes.POINTER(_c_u64)]
+        L.oracle_mc_median.restype = None
         L.oracle_mc_expected_total.argtypes = [_u32p, _c_u32, _u32p, _u32p, _c_u64,
                                                _u32p, _u32p, _c_u64]
         L.oracle_mc_expected_total.restype = ctypes.c_double
@@ -206,6 +208,25 @@ def mc_tail(totals, observed):
     ge, le = _c_u64(0), _c_u64(0)
     lib().oracle_mc_tail(totals, len(totals), int(observed), ctypes.byref(ge), ctypes.byref(le))
     return int(ge.value), int(le.value)
+
+
+def mc_median(totals):
+    """(lo, hi): the two middle order statistics of the totals (equal for odd n)."""
+    t = np.ascontiguousarray(totals, dtype=np.uint64)
+    lo, hi = _c_u64(0), _c_u64(0)
+    lib().oracle_mc_median(t, len(t), ctypes.byref(lo), ctypes.byref(hi))
+    return int(lo.value), int(hi.value)
+
+
+def enrichment(observed, lo, hi):
+    """Sec. 3.3 / Fig. 3: log2(observed / median), median = (lo + hi) / 2."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return float(np.log2(np.float64(observed) / ((np.float64(lo) + np.float64(hi)) * 0.5)))
+
+
+def decide(a_start, a_end, b_start, b_end):
+    """Sec. 1.1 sub-problem 1: does any pair intersect?  By the definition."""
+    return count_bruteforce(a_start, a_end, b_start, b_end)[1] > 0
 
 
 def pvalue(n_ge, n_shuffles):

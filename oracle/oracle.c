@@ -396,6 +396,25 @@ void oracle_mc_tail(const uint64_t *totals, uint64_t n, uint64_t observed,
     *n_le = le;
 }
 
+/* Median of the per-shuffle totals, as used by the enrichment score of      */
+/* Sec. 3.3 / Fig. 3: sort a copy, take the floor((n-1)/2)-th and the        */
+/* floor(n/2)-th values (0-based); the median is their mean.  n >= 1.        */
+static int cmp_u64(const void *a, const void *b)
+{
+    const uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return (x > y) - (x < y);
+}
+
+void oracle_mc_median(const uint64_t *totals, uint64_t n, uint64_t *lo, uint64_t *hi)
+{
+    uint64_t *c = (uint64_t *)malloc(n * sizeof(uint64_t));
+    memcpy(c, totals, n * sizeof(uint64_t));
+    qsort(c, n, sizeof(uint64_t), cmp_u64);
+    *lo = c[(n - 1) / 2];
+    *hi = c[n / 2];
+    free(c);
+}
+
 /* Exact expectation of one shuffle's total under the uniform placement     */
 /* above: a of length L on chromosome c intersects b (same chromosome) for   */
 /* starts in [b.start - L + 1, b.end], of which those in [0, len_c - L] are  */

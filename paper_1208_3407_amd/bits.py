@@ -103,6 +103,11 @@ def _load():
         "bits_enum_index_build": ([_vp, _vp, _u64, _vp, _sz, _vp, _sz, _vp], ctypes.c_int),
         "bits_scan_workspace": ([_u64, P(_sz)], ctypes.c_int),
         "bits_scan_counts": ([_vp, _u64, _vp, _vp, _sz, _vp], ctypes.c_int),
+        "bits_pvalue_lower": ([_u64, _u64], ctypes.c_double),
+        "bits_pvalue_two_sided": ([_u64, _u64, _u64], ctypes.c_double),
+        "bits_mc_median": ([_vp, _u64, _vp, _vp, _vp], ctypes.c_int),
+        "bits_enrichment": ([_u64, _u64, _u64], ctypes.c_double),
+        "bits_decide": ([P(bits_ref), _vp, _vp, _u64, _vp, _vp, P(bits_launch), _vp], ctypes.c_int),
         "bits_enum_counts": ([P(bits_ref), _vp, _vp, _u64, _vp, _vp, _vp, _vp, _sz, P(bits_launch), _vp],
                              ctypes.c_int),
         "bits_enumerate": ([_vp, _u64, _vp, _vp, _u64, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp], ctypes.c_int),
@@ -397,6 +402,42 @@ def bits_mc_pvalue(ref: Ref, a_start, a_end, chrom_len, seed: int, s0: int, s1: 
                                ctypes.c_void_p(out.n_le.data_ptr()), _lp(launch), _stream(stream)), "bits_mc_pvalue")
     out._keepalive = workspace
     return out
+
+
+def bits_pvalue_lower(n_le: int, n_shuffles: int) -> float:
+    return float(_lib.bits_pvalue_lower(n_le, n_shuffles))
+
+
+def bits_pvalue_two_sided(n_ge: int, n_le: int, n_shuffles: int) -> float:
+    return float(_lib.bits_pvalue_two_sided(n_ge, n_le, n_shuffles))
+
+
+def bits_mc_median(totals: torch.Tensor, stream=None):
+    """(lo, hi) middle order statistics of the uint64 per-shuffle totals (1-element device tensors)."""
+    dev = _device()
+    if not totals.is_cuda or totals.dtype != torch.uint64 or not totals.is_contiguous():
+        raise BitsError("totals must be a contiguous uint64 device tensor")
+    lo = torch.empty(1, dtype=torch.uint64, device=dev)
+    hi = torch.empty(1, dtype=torch.uint64, device=dev)
+    _check(_lib.bits_mc_median(_ptr(totals), totals.numel(), _ptr(lo), _ptr(hi), _stream(stream)), "bits_mc_median")
+    return lo, hi
+
+
+def bits_enrichment(observed: int, median_lo: int, median_hi: int) -> float:
+    return float(_lib.bits_enrichment(observed, median_lo, median_hi))
+
+
+def bits_decide(ref: Ref, a_start, a_end, launch=None, stream=None):
+    """Decision (1-element uint32 found, 1-element uint64 witness) device tensors."""
+    dev = _device()
+    a_start, a_end = _u32_dev(a_start, "a_start"), _u32_dev(a_end, "a_end")
+    if a_end.numel() != a_start.numel():
+        raise BitsError("a_start and a_end differ in length")
+    found = torch.empty(1, dtype=torch.uint32, device=dev)
+    witness = torch.empty(1, dtype=torch.uint64, device=dev)
+    _check(_lib.bits_decide(ctypes.byref(ref.c), _ptr(a_start), _ptr(a_end), a_start.numel(), _ptr(found),
+                            _ptr(witness), _lp(launch), _stream(stream)), "bits_decide")
+    return found, witness
 
 
 def bits_pvalue(n_ge: int, n_shuffles: int) -> float:

@@ -523,6 +523,44 @@ double bits_pvalue(uint64_t n_ge, uint64_t n_shuffles) {
     return (1.0 + (double)n_ge) / ((double)n_shuffles + 1.0);
 }
 
+double bits_pvalue_lower(uint64_t n_le, uint64_t n_shuffles) {
+    return (1.0 + (double)n_le) / ((double)n_shuffles + 1.0);
+}
+
+double bits_pvalue_two_sided(uint64_t n_ge, uint64_t n_le, uint64_t n_shuffles) {
+    const double p = 2.0 * std::min(bits_pvalue(n_ge, n_shuffles), bits_pvalue_lower(n_le, n_shuffles));
+    return p < 1.0 ? p : 1.0;
+}
+
+int bits_mc_median(const uint64_t* d_totals, uint64_t n, uint64_t* d_lo, uint64_t* d_hi, void* stream) {
+    if (!d_totals || !d_lo || !d_hi || n == 0 || n > 0xFFFFFFFFull) return BITS_E_ARG;
+    BITS_CHECK_HIP(launch_select_u64((const unsigned long long*)d_totals, n, (n - 1) / 2, n / 2,
+                                     (unsigned long long*)d_lo, (unsigned long long*)d_hi, (hipStream_t)stream));
+    return BITS_OK;
+}
+
+double bits_enrichment(uint64_t observed, uint64_t median_lo, uint64_t median_hi) {
+    const double median = ((double)median_lo + (double)median_hi) * 0.5;
+    return std::log2((double)observed / median);
+}
+
+int bits_decide(const bits_ref* ref, const uint32_t* d_a_start, const uint32_t* d_a_end, uint64_t na,
+                uint32_t* d_found, uint64_t* d_witness, const bits_launch* launch, void* stream) {
+    int rc = check_queries(ref, d_a_start, d_a_end, na);
+    if (rc != BITS_OK) return rc;
+    if (!d_found || !d_witness) return BITS_E_ARG;
+    LaunchCfg cfg;
+    rc = resolve_launch(ref, launch, &cfg);
+    if (rc != BITS_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    BITS_CHECK_HIP(launch_fill_u32(d_found, 1, 0u, s));
+    BITS_CHECK_HIP(launch_fill_u64((unsigned long long*)d_witness, 1, ~0ull, s));
+    if (ref->n == 0) return BITS_OK;
+    BITS_CHECK_HIP(launch_decide(make_search_args(ref, cfg), cfg, d_a_start, d_a_end, na, d_found,
+                                 (unsigned long long*)d_witness, s));
+    return BITS_OK;
+}
+
 // ---------------------------------------------------------------- batch
 
 struct bits_batch_plan {

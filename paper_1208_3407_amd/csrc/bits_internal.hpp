@@ -186,6 +186,10 @@ hipError_t launch_mc(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t*
                      unsigned long long* totals, unsigned long long* observed, hipStream_t s);
 hipError_t launch_rmi_window(const SearchArgs& sa, uint32_t which, const uint32_t* xs, uint64_t n, uint32_t* lo,
                              uint32_t* hi, hipStream_t s);
+hipError_t launch_decide(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
+                         uint64_t na, uint32_t* found, unsigned long long* witness, hipStream_t s);
+hipError_t launch_select_u64(const unsigned long long* v, uint64_t n, uint64_t k0, uint64_t k1,
+                             unsigned long long* out0, unsigned long long* out1, hipStream_t s);
 hipError_t launch_mc_tail(const unsigned long long* totals, uint64_t nshuf, const unsigned long long* observed,
                           unsigned long long* n_ge, unsigned long long* n_le, hipStream_t s);
 hipError_t launch_project(const uint32_t* chrom_len, uint32_t n_chrom, const uint32_t* chrom,

@@ -636,6 +636,55 @@ BITS_SEARCH_KERNEL k_count(SearchArgs sa, const uint32_t* __restrict__ a_start,
     }
 }
 
+// ------------------------------------------------------------------ decision
+// Sec. 1.1, sub-problem 1: does any a intersect any b?  The counting loop
+// with an early exit: a workgroup checks the shared flag before each tile
+// and stops once some query has a non-zero count.  *witness receives the
+// smallest index with a hit among the tiles that ran (initialised to
+// 2^64 - 1 by the caller).
+template <int QPL, bool LEARNED>
+BITS_SEARCH_KERNEL k_decide(SearchArgs sa, const uint32_t* __restrict__ a_start, const uint32_t* __restrict__ a_end,
+                            uint64_t na, uint32_t* found, unsigned long long* witness) {
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t stop;
+    if (!LEARNED) stage_tree(lds, sa.tree, sa.tree_stride, sa.depth);
+    __syncthreads();
+    const uint64_t tile = (uint64_t)blockDim.x * QPL;
+    const uint64_t ntiles = (na + tile - 1) / tile;
+    uint32_t bad = 0;
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        if (threadIdx.x == 0) stop = __hip_atomic_load(found, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        if (stop) break;
+        uint32_t as[QPL], ae[QPL], cnt[QPL], fst[QPL];
+        bool valid[QPL];
+#pragma unroll
+        for (int q = 0; q < QPL; ++q) {
+            const uint64_t i = t * tile + (uint64_t)q * blockDim.x + threadIdx.x;
+            valid[q] = i < na;
+            as[q] = valid[q] ? a_start[i] : 0u;
+            ae[q] = valid[q] ? a_end[i] : 0u;
+            if (as[q] > ae[q]) {
+                bad = 1;
+                valid[q] = false;
+                ae[q] = as[q];
+            }
+        }
+        icount<QPL, LEARNED>(sa, lds, as, ae, cnt, fst);
+        bool hit = false;
+#pragma unroll
+        for (int q = 0; q < QPL; ++q) {
+            if (valid[q] && cnt[q]) {
+                atomicMin(witness, (unsigned long long)(t * tile + (uint64_t)q * blockDim.x + threadIdx.x));
+                hit = true;
+            }
+        }
+        if (hit) atomicOr(found, 1u);
+        __syncthreads();   // every lane has read `stop` before it is rewritten
+    }
+    if (bad) atomicOr(sa.status, BITS_FLAG_INTERVAL);
+}
+
 // ------------------------------------------------------------------ Monte-Carlo
 // The per-query table (off, span, len, idx) is grouped by chromosome (see
 // k_mc_prepare): position j holds query idx[j].  Work item = (tile of
@@ -852,6 +901,48 @@ __global__ void k_mc_tail(const unsigned long long* __restrict__ totals, uint64_
         }
         *n_ge = g;
         *n_le = l;
+    }
+}
+
+// Order statistics of the per-shuffle totals (the median of Sec. 3.3):
+// out[r] = the k[r]-th smallest (0-based) of v[0..n), by most-significant-
+// digit radix selection over the 8 bytes: each pass histograms the values
+// that match the digits fixed so far and keeps the bucket holding the rank.
+// One workgroup; exact for any n < 2^32.
+__global__ void __launch_bounds__(1024) k_select_u64(const unsigned long long* __restrict__ v, uint64_t n,
+                                                     uint64_t k0, uint64_t k1, unsigned long long* out0,
+                                                     unsigned long long* out1) {
+    __shared__ uint32_t hist[256];
+    __shared__ unsigned long long sh_prefix, sh_mask;
+    __shared__ uint64_t sh_rank;
+    for (int which = 0; which < 2; ++which) {
+        if (threadIdx.x == 0) {
+            sh_prefix = 0ull;
+            sh_mask = 0ull;
+            sh_rank = which ? k1 : k0;
+        }
+        __syncthreads();
+        for (int p = 7; p >= 0; --p) {
+            for (uint32_t d = threadIdx.x; d < 256u; d += blockDim.x) hist[d] = 0u;
+            __syncthreads();
+            const unsigned long long prefix = sh_prefix, mask = sh_mask;
+            for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) {
+                const unsigned long long x = v[i];
+                if ((x & mask) == prefix) atomicAdd(&hist[(uint32_t)(x >> (8 * p)) & 255u], 1u);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint64_t r = sh_rank, cum = 0;
+                uint32_t d = 0;
+                while (d < 255u && cum + hist[d] <= r) cum += hist[d++];
+                sh_rank = r - cum;
+                sh_prefix = prefix | ((unsigned long long)d << (8 * p));
+                sh_mask = mask | (0xFFull << (8 * p));
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *(which ? out1 : out0) = sh_prefix;
+        __syncthreads();
     }
 }
 
@@ -1148,6 +1239,37 @@ hipError_t launch_mc(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t*
         default: return L ? launch_mc_t<2, true>(sa, cfg, as, ae, tab, na, seed, s0, nshuf, totals, observed, s)
                           : launch_mc_t<2, false>(sa, cfg, as, ae, tab, na, seed, s0, nshuf, totals, observed, s);
     }
+}
+
+template <int QPL, bool LEARNED>
+static hipError_t launch_decide_t(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
+                                  uint64_t na, uint32_t* found, unsigned long long* witness, hipStream_t s) {
+    const size_t lds = search_lds_bytes(LEARNED, sa.depth, QPL, cfg.block);
+    const uint64_t tile = (uint64_t)cfg.block * QPL;
+    const void* kern = (const void*)k_decide<QPL, LEARNED>;
+    const uint32_t grid = persistent_grid(kern, cfg, lds, (na + tile - 1) / tile);
+    hipLaunchKernelGGL((k_decide<QPL, LEARNED>), dim3(grid), dim3(cfg.block), lds, s, sa, as, ae, na, found, witness);
+    return hipGetLastError();
+}
+
+hipError_t launch_decide(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
+                         uint64_t na, uint32_t* found, unsigned long long* witness, hipStream_t s) {
+    if (!na) return hipSuccess;
+    const bool L = cfg.path == BITS_PATH_LEARNED;
+    switch (cfg.qpl) {
+        case 1: return L ? launch_decide_t<1, true>(sa, cfg, as, ae, na, found, witness, s)
+                         : launch_decide_t<1, false>(sa, cfg, as, ae, na, found, witness, s);
+        case 4: return L ? launch_decide_t<4, true>(sa, cfg, as, ae, na, found, witness, s)
+                         : launch_decide_t<4, false>(sa, cfg, as, ae, na, found, witness, s);
+        default: return L ? launch_decide_t<2, true>(sa, cfg, as, ae, na, found, witness, s)
+                          : launch_decide_t<2, false>(sa, cfg, as, ae, na, found, witness, s);
+    }
+}
+
+hipError_t launch_select_u64(const unsigned long long* v, uint64_t n, uint64_t k0, uint64_t k1,
+                             unsigned long long* out0, unsigned long long* out1, hipStream_t s) {
+    hipLaunchKernelGGL(k_select_u64, dim3(1), dim3(1024), 0, s, v, n, k0, k1, out0, out1);
+    return hipGetLastError();
 }
 
 hipError_t launch_mc_tail(const unsigned long long* totals, uint64_t nshuf, const unsigned long long* observed,

@@ -86,3 +86,26 @@ def test_bad_arguments_rejected_before_any_device_work(lib):
     assert lib.bits_project(big, 2, None, None, None, ctypes.c_uint64(0), None, None, None, None) == 3
     assert lib.bits_rmi_leaf_grad(None, None, 5000, None, None, None, None) == 1
     assert lib.bits_batch_create(None, 0, None, None, None, 0, None, None, ctypes.c_size_t(0), None, None, None) == 1
+
+
+def test_host_statistics(lib):
+    """Host-side helpers of the Monte-Carlo statistics: tails and enrichment
+    against closed forms and the oracle's definition (no device needed)."""
+    import math
+    import oracle
+    lib.bits_pvalue_lower.restype = ctypes.c_double
+    lib.bits_pvalue_lower.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    lib.bits_pvalue_two_sided.restype = ctypes.c_double
+    lib.bits_pvalue_two_sided.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
+    lib.bits_enrichment.restype = ctypes.c_double
+    lib.bits_enrichment.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
+    assert lib.bits_pvalue_lower(0, 9999) == 1.0 / 10000.0
+    assert lib.bits_pvalue_two_sided(0, 9999, 9999) == 2.0 / 10000.0
+    assert lib.bits_pvalue_two_sided(9999, 9999, 9999) == 1.0
+    assert lib.bits_pvalue_two_sided(4, 99, 99) == 2.0 * 5.0 / 100.0
+    assert lib.bits_enrichment(200, 100, 100) == 1.0
+    assert lib.bits_enrichment(7, 7, 7) == 0.0
+    assert lib.bits_enrichment(0, 5, 5) == -math.inf
+    assert lib.bits_enrichment(5, 0, 0) == math.inf
+    for obs, lo, hi in ((123456, 1000, 1003), (1, 2**40, 2**40 + 1), (10**12, 7, 8)):
+        assert lib.bits_enrichment(obs, lo, hi) == oracle.enrichment(obs, lo, hi)

@@ -1,0 +1,109 @@
+"""GPU parity of the decision sub-problem (Sec. 1.1) and of the Monte-Carlo
+summary statistics (median of the per-shuffle totals, enrichment score of
+Sec. 3.3) through the C ABI, against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+from paper_1208_3407_amd import bits, datagen  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+
+
+def up(x, dtype=np.uint32):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=dtype))).to(DEV)
+
+
+def down(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 1000, 1001, 10_000, 65_537])
+def test_median_of_totals(n):
+    note("case: median n=%d" % n)
+    r = np.random.default_rng(n)
+    for hi in (3, 10**9, 2**63):
+        t = r.integers(0, hi, n, dtype=np.uint64)
+        lo_d, hi_d = bits.bits_mc_median(up(t, np.uint64))
+        assert (int(down(lo_d)[0]), int(down(hi_d)[0])) == oracle.mc_median(t), hi
+
+
+def test_median_and_enrichment_of_a_monte_carlo_run():
+    """The summary of a real run: median of the device totals, the enrichment
+    score and the tails, each against the oracle's own totals."""
+    note("case: MC summary")
+    lengths, A, B = datagen.w2_sets(seed=2, n_a=2000, n_b=40_000)
+    a_s, a_e = oracle.project(lengths, A.chrom, A.start, A.end)
+    b_s, b_e = oracle.project(lengths, B.chrom, B.start, B.end)
+    exp = oracle.mc_totals(np.sort(b_s), np.sort(b_e), oracle.mc_prepare(lengths, a_s, a_e), 7, 0, 101, threads=8)
+    obs = oracle.counter(a_s, a_e, b_s, b_e)[1]
+    ref = bits.bits_sort_ref(up(b_s), up(b_e), learned=True, train={"epochs": 10})
+    mc = bits.bits_mc_pvalue(ref, up(a_s), up(a_e), lengths, 7, 0, 101)
+    assert np.array_equal(down(mc.totals), exp)
+    lo, hi = bits.bits_mc_median(mc.totals)
+    lo, hi = int(down(lo)[0]), int(down(hi)[0])
+    assert (lo, hi) == oracle.mc_median(exp)
+    assert bits.bits_enrichment(obs, lo, hi) == oracle.enrichment(obs, lo, hi)
+    ge, le = int(down(mc.n_ge)[0]), int(down(mc.n_le)[0])
+    assert bits.bits_pvalue_lower(le, 101) == (1.0 + le) / 102.0
+    assert bits.bits_pvalue_two_sided(ge, le, 101) == min(1.0, 2.0 * min((1.0 + ge) / 102.0, (1.0 + le) / 102.0))
+
+
+LAUNCHES = [{"path": bits.BITS_PATH_PLAIN}, {"path": bits.BITS_PATH_PLAIN, "block": 256, "qpl": 1, "grid": 3},
+            {"path": bits.BITS_PATH_LEARNED}, {"path": bits.BITS_PATH_LEARNED, "block": 512, "qpl": 4}]
+
+
+def check_decide(ref, a_s, a_e, b_s, b_e, lp):
+    found, wit = bits.bits_decide(ref, up(a_s), up(a_e), launch=lp)
+    f, w = int(down(found)[0]), int(down(wit)[0])
+    ok = a_s <= a_e
+    counts = oracle.counter(a_s[ok], a_e[ok], b_s, b_e)[0] if ok.any() else np.zeros(0, np.uint32)
+    exp = bool(np.any(counts > 0))
+    assert f == int(exp), lp
+    if exp:
+        idx = np.flatnonzero(ok)
+        assert w < len(a_s) and ok[w] and counts[np.searchsorted(idx, w)] > 0, lp
+    else:
+        assert w == 2**64 - 1, lp
+
+
+def test_decide():
+    note("case: decide")
+    r = np.random.default_rng(4)
+    b_s = (r.integers(0, 10**6, 50_000) * 20).astype(np.uint32)        # starts at multiples of 20
+    b_e = b_s + np.uint32(9)                                           # [20k, 20k + 9]
+    ref = bits.bits_sort_ref(up(b_s), up(b_e), learned=True, train={"epochs": 10})
+    gap_s = (r.integers(0, 10**6, 300_000) * 20 + 10).astype(np.uint32)  # [20k + 10, 20k + 19]: in the gaps
+    gap_e = gap_s + np.uint32(9)
+    for lp in LAUNCHES:
+        note("  launch %s" % lp)
+        check_decide(ref, gap_s, gap_e, b_s, b_e, lp)                  # no intersection anywhere
+        hit_s, hit_e = gap_s.copy(), gap_e.copy()
+        hit_s[-1], hit_e[-1] = b_e[7], b_e[7] + 5                     # only the last query touches one interval
+        check_decide(ref, hit_s, hit_e, b_s, b_e, lp)
+        check_decide(ref, b_s, b_e, b_s, b_e, lp)                      # everything intersects
+        bad_s, bad_e = hit_s.copy(), hit_e.copy()
+        bad_s[5], bad_e[5] = 100, 50                                   # start > end: skipped and flagged
+        check_decide(ref, bad_s, bad_e, b_s, b_e, lp)
+        assert bits.bits_get_status(ref) & bits.BITS_FLAG_INTERVAL
+        bits.bits_clear_status(ref)
+    # empty reference, empty query set
+    empty = bits.bits_sort_ref(up(np.zeros(0)), up(np.zeros(0)))
+    found, wit = bits.bits_decide(empty, up([1]), up([5]))
+    assert int(down(found)[0]) == 0 and int(down(wit)[0]) == 2**64 - 1
+    found, wit = bits.bits_decide(ref, up(np.zeros(0)), up(np.zeros(0)))
+    assert int(down(found)[0]) == 0

@@ -428,3 +428,33 @@ def test_enumeration_oracle_random():
         assert len(np.unique(pa.astype(np.uint64) * nb + pb)) == len(pa)
         assert np.array_equal(np.bincount(pa, minlength=na), _np_count(a_s, a_e, b_s, b_e))
         assert len(pa) == oracle.sweep_total(a_s, a_e, b_s, b_e)
+
+
+def test_median_and_enrichment_oracle():
+    """The median of the totals equals numpy's median (library routine) on odd,
+    even and tied samples; the enrichment score has its closed forms."""
+    r = np.random.default_rng(3)
+    for n in (1, 2, 3, 10, 999, 1000, 10_000):
+        for hi in (5, 10**6, 2**50):
+            t = r.integers(0, hi, n, dtype=np.uint64)
+            lo_v, hi_v = oracle.mc_median(t)
+            assert (lo_v + hi_v) / 2 == np.median(t.astype(np.float64))
+            assert lo_v <= hi_v and np.sum(t < lo_v) <= (n - 1) // 2 < np.sum(t <= lo_v)
+    assert oracle.enrichment(200, 100, 100) == 1.0
+    assert oracle.enrichment(100, 99, 101) == 0.0
+    assert oracle.enrichment(25, 100, 100) == -2.0
+    assert oracle.enrichment(0, 3, 3) == -np.inf
+
+
+def test_decision_oracle():
+    """Sub-problem 1 is 'some count is non-zero': disjoint sets, one touching
+    pair (closed intervals), and random sets against numpy searchsorted."""
+    assert not oracle.decide([0, 20], [9, 29], [10, 30], [19, 39])
+    assert oracle.decide([0, 20], [10, 29], [10, 30], [19, 39])
+    r = np.random.default_rng(8)
+    for _ in range(20):
+        b_s = r.integers(0, 10**6, 50).astype(np.uint32)
+        b_e = b_s + r.integers(0, 100, 50).astype(np.uint32)
+        a_s = r.integers(0, 10**6, 30).astype(np.uint32)
+        a_e = a_s + r.integers(0, 100, 30).astype(np.uint32)
+        assert oracle.decide(a_s, a_e, b_s, b_e) == bool(np.any(_np_count(a_s, a_e, b_s, b_e) > 0))
