@@ -288,6 +288,21 @@ def main():
     significance["decide_ms"] = t_decide
     significance["decide_found"] = int(bits.bits_decide(ref, a_s, a_e, launch=lp_learned)[0].item())
 
+    # the paper's Monte-Carlo orientation (B randomised and re-sorted every round) against this
+    # library's fixed-index loop on the same draws: 1e6 x 1e6 intervals, 100 rounds
+    n_po, r_po = 1_000_000, 100
+    pa_s, pa_e, pb_s, pb_e = a_s[:n_po], a_e[:n_po], b_s[:n_po], b_e[:n_po]
+    ref_po = bits.bits_sort_ref(pa_s, pa_e, learned=True, train=train)
+    po = {}
+    t_resort = timed(lambda: po.__setitem__("r", bits.bits_mc_resort(pa_s, pa_e, pb_s, pb_e, lengths, MC_SEED, 0,
+                                                                     r_po)), reps=2)
+    t_fixed = timed(lambda: po.__setitem__("f", bits.bits_mc_pvalue(ref_po, pb_s, pb_e, lengths, MC_SEED, 0, r_po)),
+                    reps=2)
+    paper_orientation = {"size": n_po, "rounds": r_po, "resort_ms_per_round": t_resort / r_po,
+                         "fixed_index_ms_per_round": t_fixed / r_po,
+                         "totals_equal": bool(torch.equal(po["r"].totals, po["f"].totals))}
+    del ref_po, po
+
     mc_avg = float(np.mean(phase["mc_ms"]))
     mc_evals = N_SHUF * N_MC + N_MC
     achieved = BYTES_PER_EVAL_LEARNED * mc_evals / (mc_avg / 1e3) / 1e9
@@ -319,6 +334,7 @@ def main():
         "rmi": info,
         "enumeration": enumeration,
         "significance": significance,
+        "paper_orientation": paper_orientation,
         "status": status,
         "roofline": {"bound": "hbm", "kernel": "k_mc<learned> (Monte-Carlo shuffles)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -283,6 +283,30 @@ int bits_mc_pvalue(const bits_ref *ref, const uint32_t *d_a_start, const uint32_
                    uint64_t *d_observed, uint64_t *d_n_ge, uint64_t *d_n_le,
                    const bits_launch *launch, void *stream);
 
+/* Workspace bytes of bits_mc_resort for |B| = nb and `batch` rounds per
+ * sort launch (1 <= batch <= 4096): 16 bytes per interval of B, 16 bytes per
+ * interval per round of the batch, and the segmented sort's workspace. */
+int bits_mc_resort_workspace(uint64_t nb, uint32_t batch, size_t *bytes);
+
+/* The Monte-Carlo loop in the paper's orientation (Sec. 3.2, Table 1): every
+ * round randomises the DATABASE set B within its chromosomes (rule and
+ * Philox stream of bits_mc_pvalue with the roles of A and B swapped: round s
+ * places interval j of B with counter g = s * nb + j), sorts B_S and B_E
+ * again on the device (segmented radix sort, `batch` rounds per launch) and
+ * counts the fixed query set A against it by plain bisection.  The count is
+ * symmetric in A and B, so the per-round totals equal bits_mc_pvalue's with
+ * a reference built from A and B as the queries, which needs no per-round
+ * sort; this entry point is the literal form, for comparison.
+ *   d_a_*, na       the fixed query set A (projected; no end of 2^32 - 1)
+ *   d_b_*, nb       the database set B (projected, < 2^32 intervals); an interval
+ *                   outside its chromosome sets BITS_FLAG_CHROM in d_status and
+ *                   is left out of every round and of the observed total
+ *   outputs         as bits_mc_pvalue (d_status nullable) */
+int bits_mc_resort(const uint32_t *d_a_start, const uint32_t *d_a_end, uint64_t na, const uint32_t *d_b_start,
+                   const uint32_t *d_b_end, uint64_t nb, const uint32_t *chrom_len, uint32_t n_chrom, uint64_t seed,
+                   uint64_t s0, uint64_t s1, uint32_t batch, void *d_ws, size_t ws_bytes, uint64_t *d_totals,
+                   uint64_t *d_observed, uint64_t *d_n_ge, uint64_t *d_n_le, uint32_t *d_status, void *stream);
+
 /* (1 + n_ge) / (n_shuffles + 1) as one IEEE fp64 division (host). */
 double bits_pvalue(uint64_t n_ge, uint64_t n_shuffles);
 

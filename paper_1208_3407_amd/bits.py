@@ -103,6 +103,9 @@ def _load():
         "bits_enum_index_build": ([_vp, _vp, _u64, _vp, _sz, _vp, _sz, _vp], ctypes.c_int),
         "bits_scan_workspace": ([_u64, P(_sz)], ctypes.c_int),
         "bits_scan_counts": ([_vp, _u64, _vp, _vp, _sz, _vp], ctypes.c_int),
+        "bits_mc_resort_workspace": ([_u64, _u32, P(_sz)], ctypes.c_int),
+        "bits_mc_resort": ([_vp, _vp, _u64, _vp, _vp, _u64, P(_u32), _u32, _u64, _u64, _u64, _u32, _vp, _sz, _vp,
+                            _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
         "bits_pvalue_lower": ([_u64, _u64], ctypes.c_double),
         "bits_pvalue_two_sided": ([_u64, _u64, _u64], ctypes.c_double),
         "bits_mc_median": ([_vp, _u64, _vp, _vp, _vp], ctypes.c_int),
@@ -401,6 +404,36 @@ def bits_mc_pvalue(ref: Ref, a_start, a_end, chrom_len, seed: int, s0: int, s1: 
                                ctypes.c_void_p(out.observed.data_ptr()), ctypes.c_void_p(out.n_ge.data_ptr()),
                                ctypes.c_void_p(out.n_le.data_ptr()), _lp(launch), _stream(stream)), "bits_mc_pvalue")
     out._keepalive = workspace
+    return out
+
+
+def bits_mc_resort_workspace(nb: int, batch: int) -> int:
+    n = _sz(0)
+    _check(_lib.bits_mc_resort_workspace(nb, batch, ctypes.byref(n)), "bits_mc_resort_workspace")
+    return n.value
+
+
+def bits_mc_resort(a_start, a_end, b_start, b_end, chrom_len, seed: int, s0: int, s1: int, batch: int = 64,
+                   workspace: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None,
+                   stream=None) -> "MCResult":
+    """The paper's Monte-Carlo orientation: B randomised and re-sorted every round, A fixed."""
+    dev = _device()
+    a_start, a_end = _u32_dev(a_start, "a_start"), _u32_dev(a_end, "a_end")
+    b_start, b_end = _u32_dev(b_start, "b_start"), _u32_dev(b_end, "b_end")
+    nb = b_start.numel()
+    if a_end.numel() != a_start.numel() or b_end.numel() != nb:
+        raise BitsError("start and end arrays differ in length")
+    if workspace is None:
+        workspace = _scratch(bits_mc_resort_workspace(nb, batch), dev)
+    lens = _host_u32(chrom_len)
+    ns = s1 - s0
+    out = MCResult(torch.empty(max(ns, 1), dtype=torch.uint64, device=dev)[:ns],
+                   torch.empty(1, dtype=torch.uint64, device=dev), torch.empty(1, dtype=torch.uint64, device=dev),
+                   torch.empty(1, dtype=torch.uint64, device=dev))
+    _check(_lib.bits_mc_resort(_ptr(a_start), _ptr(a_end), a_start.numel(), _ptr(b_start), _ptr(b_end), nb, lens,
+                               len(lens), seed, s0, s1, batch, _ptr(workspace), workspace.numel(),
+                               _ptr(out.totals), _ptr(out.observed), _ptr(out.n_ge), _ptr(out.n_le), _ptr(status),
+                               _stream(stream)), "bits_mc_resort")
     return out
 
 

@@ -519,6 +519,103 @@ int bits_enumerate(const void* d_index, uint64_t n, const uint32_t* d_a_start, c
     return BITS_OK;
 }
 
+// ---------------------------------------------------------------- paper orientation
+
+namespace {
+struct ResortWs {
+    size_t tab, status, s_in, e_in, s_out, e_out, sort, total;
+    size_t seg;   // bytes of one round's keys
+};
+ResortWs resort_ws(uint64_t nb, uint32_t batch) {
+    ResortWs W;
+    size_t o = 0;
+    const size_t col = align256((size_t)nb * sizeof(uint32_t));
+    W.seg = (size_t)nb * sizeof(uint32_t);
+    W.tab = o; o += 4 * col + 2 * align256(BITS_MAX_CHROM * sizeof(uint32_t));
+    W.status = o; o += 256;   // status word used when the caller passes none
+    const size_t keys = align256((size_t)batch * W.seg);
+    W.s_in = o; o += keys;
+    W.e_in = o; o += keys;
+    W.s_out = o; o += keys;
+    W.e_out = o; o += keys;
+    W.sort = o;
+    std::vector<uint64_t> ns(2 * (size_t)batch, nb);
+    o += align256(sort_workspace_bytes(ns.data(), 2 * batch));
+    W.total = o;
+    return W;
+}
+}  // namespace
+
+int bits_mc_resort_workspace(uint64_t nb, uint32_t batch, size_t* bytes) {
+    if (!bytes || nb > 0xFFFFFFFFull || batch == 0 || batch > 4096) return BITS_E_ARG;
+    *bytes = resort_ws(nb, batch).total;
+    return BITS_OK;
+}
+
+int bits_mc_resort(const uint32_t* d_a_start, const uint32_t* d_a_end, uint64_t na, const uint32_t* d_b_start,
+                   const uint32_t* d_b_end, uint64_t nb, const uint32_t* chrom_len, uint32_t n_chrom, uint64_t seed,
+                   uint64_t s0, uint64_t s1, uint32_t batch, void* d_ws, size_t ws_bytes, uint64_t* d_totals,
+                   uint64_t* d_observed, uint64_t* d_n_ge, uint64_t* d_n_le, uint32_t* d_status, void* stream) {
+    if (nb > 0xFFFFFFFFull || s1 < s0 || batch == 0 || batch > 4096) return BITS_E_ARG;
+    if (!chrom_len || n_chrom == 0 || n_chrom > BITS_MAX_CHROM) return BITS_E_ARG;
+    if (!d_observed || !d_n_ge || !d_n_le || (s1 > s0 && !d_totals)) return BITS_E_ARG;
+    if ((na && (!d_a_start || !d_a_end)) || (nb && (!d_b_start || !d_b_end))) return BITS_E_ARG;
+    const uint64_t ns = s1 - s0;
+    if (nb && s1 > (~0ull - nb) / nb) return BITS_E_ARG;   // counter g = s * nb + j must not wrap
+    uint64_t g = 0;
+    for (uint32_t c = 0; c < n_chrom; ++c) g += chrom_len[c];
+    if (g > 0xFFFFFFFFull) return BITS_E_CHROM;
+    const ResortWs W = resort_ws(nb, batch);
+    if (nb && (!d_ws || ws_bytes < W.total || ((uintptr_t)d_ws & 255u))) return BITS_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    auto* totals = (unsigned long long*)d_totals;
+    auto* obs = (unsigned long long*)d_observed;
+    BITS_CHECK_HIP(launch_fill_u64(totals, ns, 0ull, s));
+    BITS_CHECK_HIP(launch_fill_u64(obs, 1, 0ull, s));
+    if (nb && na) {
+        char* w = (char*)d_ws;
+        const size_t col = align256((size_t)nb * sizeof(uint32_t)), cstride = align256(BITS_MAX_CHROM * 4);
+        McTable tab;
+        tab.off = (uint32_t*)(w + W.tab);
+        tab.span = (uint32_t*)(w + W.tab + col);
+        tab.len = (uint32_t*)(w + W.tab + 2 * col);
+        tab.idx = (uint32_t*)(w + W.tab + 3 * col);
+        tab.hist = (uint32_t*)(w + W.tab + 4 * col);
+        tab.cursor = (uint32_t*)(w + W.tab + 4 * col + cstride);
+        uint32_t* S_in = (uint32_t*)(w + W.s_in);
+        uint32_t* E_in = (uint32_t*)(w + W.e_in);
+        uint32_t* S_out = (uint32_t*)(w + W.s_out);
+        uint32_t* E_out = (uint32_t*)(w + W.e_out);
+        void* sort_ws = w + W.sort;
+        const size_t sort_bytes = W.total - W.sort;
+        // B's per-interval table (chromosome offset, legal starts, length, index), computed once
+        uint32_t* status = d_status ? d_status : (uint32_t*)(w + W.status);
+        BITS_CHECK_HIP(launch_mc_prepare(d_b_start, d_b_end, nb, chrom_len, n_chrom, tab, status, s));
+        auto run = [&](uint64_t first, uint32_t rounds, bool identity, unsigned long long* out) -> int {
+            BITS_CHECK_HIP(launch_place_rounds(tab, d_b_start, nb, seed, first, rounds, identity, S_in, E_in, s));
+            std::vector<SortSeg> segs;
+            segs.reserve(2 * (size_t)rounds);
+            for (uint32_t r = 0; r < rounds; ++r) {
+                segs.push_back({S_in + (size_t)r * nb, S_out + (size_t)r * nb, nb});
+                segs.push_back({E_in + (size_t)r * nb, E_out + (size_t)r * nb, nb});
+            }
+            const int rc = launch_sort(segs.data(), 2 * rounds, sort_ws, sort_bytes, s);
+            if (rc != BITS_OK) return rc;
+            BITS_CHECK_HIP(launch_count_rounds(S_out, E_out, nb, rounds, d_a_start, d_a_end, na, out, status, s));
+            return BITS_OK;
+        };
+        int rc = run(0, 1, true, obs);
+        if (rc != BITS_OK) return rc;
+        for (uint64_t b = 0; b < ns; b += batch) {
+            const uint32_t r = (uint32_t)std::min<uint64_t>(batch, ns - b);
+            rc = run(s0 + b, r, false, totals + b);
+            if (rc != BITS_OK) return rc;
+        }
+    }
+    BITS_CHECK_HIP(launch_mc_tail(totals, ns, obs, (unsigned long long*)d_n_ge, (unsigned long long*)d_n_le, s));
+    return BITS_OK;
+}
+
 double bits_pvalue(uint64_t n_ge, uint64_t n_shuffles) {
     return (1.0 + (double)n_ge) / ((double)n_shuffles + 1.0);
 }

@@ -190,6 +190,11 @@ hipError_t launch_decide(const SearchArgs& sa, const LaunchCfg& cfg, const uint3
                          uint64_t na, uint32_t* found, unsigned long long* witness, hipStream_t s);
 hipError_t launch_select_u64(const unsigned long long* v, uint64_t n, uint64_t k0, uint64_t k1,
                              unsigned long long* out0, unsigned long long* out1, hipStream_t s);
+hipError_t launch_place_rounds(const McTable& tab, const uint32_t* b_start, uint64_t nb, uint64_t seed, uint64_t s0,
+                               uint32_t rounds, bool identity, uint32_t* S, uint32_t* E, hipStream_t s);
+hipError_t launch_count_rounds(const uint32_t* S, const uint32_t* E, uint64_t nb, uint32_t rounds, const uint32_t* as,
+                               const uint32_t* ae, uint64_t na, unsigned long long* totals, uint32_t* status,
+                               hipStream_t s);
 hipError_t launch_mc_tail(const unsigned long long* totals, uint64_t nshuf, const unsigned long long* observed,
                           unsigned long long* n_ge, unsigned long long* n_le, hipStream_t s);
 hipError_t launch_project(const uint32_t* chrom_len, uint32_t n_chrom, const uint32_t* chrom,

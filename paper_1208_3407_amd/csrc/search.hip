@@ -875,6 +875,85 @@ __global__ void __launch_bounds__(1024) k_mc_prepare(const uint32_t* __restrict_
     if (bad) atomicOr(status, bad);
 }
 
+// ------------------------------------------------------------------ paper orientation
+// The Monte-Carlo loop as Sec. 3.2 runs it: every round randomises the
+// database set B and sorts it again, then counts the fixed query set A.
+// Round r of a batch places interval idx[p] of B (table position p) by the
+// rule and stream of k_mc with the roles swapped, g = (s0 + r) * nb + idx[p],
+// and writes keys S[r * nb + p], E[r * nb + p] as one segment per round for
+// the segmented sort.  An interval outside its chromosome (span 0) becomes
+// the sentinel [2^32 - 1, 2^32 - 1], which no query with end < 2^32 - 1
+// counts.  identity = true writes the unshuffled set (the observed round).
+__global__ void k_place_rounds(const uint32_t* __restrict__ off, const uint32_t* __restrict__ span,
+                               const uint32_t* __restrict__ len, const uint32_t* __restrict__ idx,
+                               const uint32_t* __restrict__ b_start, uint64_t nb, uint64_t seed, uint64_t s0,
+                               uint32_t rounds, uint32_t identity, uint32_t* __restrict__ S, uint32_t* __restrict__ E) {
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint64_t total = (uint64_t)rounds * nb;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t r = t / nb, p = t - r * nb;
+        const uint32_t sp = span[p];
+        uint32_t st = 0xFFFFFFFFu, en = 0xFFFFFFFFu;
+        if (sp) {
+            if (identity) {
+                st = b_start[idx[p]];
+            } else {
+                const uint64_t g = (s0 + r) * nb + idx[p];
+                uint32_t c0 = (uint32_t)g, c1 = (uint32_t)(g >> 32), c2 = 0u, c3 = 0u;
+                philox4x32_10(c0, c1, c2, c3, k0, k1);
+                const uint64_t u = ((uint64_t)c1 << 32) | c0;
+                st = off[p] + (uint32_t)__umul64hi(u, (uint64_t)sp);
+            }
+            en = st + len[p] - 1u;
+        }
+        S[t] = st;
+        E[t] = en;
+    }
+}
+
+// Counts the fixed query set A against every sorted round of a batch
+// (segments S[r * nb ..], E[r * nb ..]) by plain bisection of the whole
+// segment (no top tree: the arrays change every round).  Work item = (round,
+// tile of A); one atomic per wave per item into totals[r].
+template <int QPL>
+BITS_SEARCH_KERNEL k_count_rounds(SearchArgs sa0, const uint32_t* __restrict__ S, const uint32_t* __restrict__ E,
+                                  uint64_t nb, uint32_t rounds, const uint32_t* __restrict__ a_start,
+                                  const uint32_t* __restrict__ a_end, uint64_t na, uint64_t tiles,
+                                  unsigned long long* __restrict__ totals) {
+    const uint64_t tile = (uint64_t)blockDim.x * QPL;
+    uint32_t bad = 0;
+    for (uint64_t item = blockIdx.x; item < (uint64_t)rounds * tiles; item += gridDim.x) {
+        const uint64_t r = item / tiles, t = item - r * tiles;
+        SearchArgs sa = sa0;
+        sa.bs = S + r * nb;
+        sa.be = E + r * nb;
+        sa.n = (uint32_t)nb;
+        sa.depth = 0;
+        uint32_t as[QPL], ae[QPL], cnt[QPL], fst[QPL];
+        bool valid[QPL];
+#pragma unroll
+        for (int q = 0; q < QPL; ++q) {
+            const uint64_t i = t * tile + (uint64_t)q * blockDim.x + threadIdx.x;
+            valid[q] = i < na;
+            as[q] = valid[q] ? a_start[i] : 0u;
+            ae[q] = valid[q] ? a_end[i] : 0u;
+            if (as[q] > ae[q]) {
+                bad = 1;
+                valid[q] = false;
+                ae[q] = as[q];
+            }
+        }
+        icount_plain<QPL>(sa, nullptr, as, ae, cnt, fst);
+        uint64_t sum = 0;
+#pragma unroll
+        for (int q = 0; q < QPL; ++q) sum += valid[q] ? cnt[q] : 0u;
+        sum = wave_sum_u64(sum);
+        if ((threadIdx.x & (kWave - 1)) == 0 && sum) atomicAdd(totals + r, (unsigned long long)sum);
+    }
+    if (bad && sa0.status) atomicOr(sa0.status, BITS_FLAG_INTERVAL);
+}
+
 __global__ void k_mc_tail(const unsigned long long* __restrict__ totals, uint64_t nshuf,
                           const unsigned long long* observed, unsigned long long* n_ge,
                           unsigned long long* n_le) {
@@ -1269,6 +1348,36 @@ hipError_t launch_decide(const SearchArgs& sa, const LaunchCfg& cfg, const uint3
 hipError_t launch_select_u64(const unsigned long long* v, uint64_t n, uint64_t k0, uint64_t k1,
                              unsigned long long* out0, unsigned long long* out1, hipStream_t s) {
     hipLaunchKernelGGL(k_select_u64, dim3(1), dim3(1024), 0, s, v, n, k0, k1, out0, out1);
+    return hipGetLastError();
+}
+
+hipError_t launch_place_rounds(const McTable& tab, const uint32_t* b_start, uint64_t nb, uint64_t seed, uint64_t s0,
+                               uint32_t rounds, bool identity, uint32_t* S, uint32_t* E, hipStream_t s) {
+    const uint64_t total = (uint64_t)rounds * nb;
+    if (!total) return hipSuccess;
+    uint64_t g = (total + 255) / 256;
+    if (g > 16384) g = 16384;
+    hipLaunchKernelGGL(k_place_rounds, dim3((uint32_t)g), dim3(256), 0, s, tab.off, tab.span, tab.len, tab.idx,
+                       b_start, nb, seed, s0, rounds, identity ? 1u : 0u, S, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_rounds(const uint32_t* S, const uint32_t* E, uint64_t nb, uint32_t rounds, const uint32_t* as,
+                               const uint32_t* ae, uint64_t na, unsigned long long* totals, uint32_t* status,
+                               hipStream_t s) {
+    if (!na || !rounds) return hipSuccess;
+    constexpr int QPL = 2;
+    const uint32_t block = 256;
+    const uint64_t tile = (uint64_t)block * QPL;
+    const uint64_t tiles = (na + tile - 1) / tile;
+    SearchArgs sa{};
+    sa.status = status;
+    sa.n = (uint32_t)nb;
+    LaunchCfg cfg{block, QPL, 0, 0, BITS_PATH_PLAIN};
+    const void* kern = (const void*)k_count_rounds<QPL>;
+    const uint32_t grid = persistent_grid(kern, cfg, 0, (uint64_t)rounds * tiles);
+    hipLaunchKernelGGL(k_count_rounds<QPL>, dim3(grid), dim3(block), 0, s, sa, S, E, nb, rounds, as, ae, na, tiles,
+                       totals);
     return hipGetLastError();
 }
 

@@ -107,3 +107,51 @@ def test_decide():
     assert int(down(found)[0]) == 0 and int(down(wit)[0]) == 2**64 - 1
     found, wit = bits.bits_decide(ref, up(np.zeros(0)), up(np.zeros(0)))
     assert int(down(found)[0]) == 0
+
+
+@pytest.mark.parametrize("batch", [1, 7, 64])
+def test_paper_orientation_resort(batch):
+    """Sec. 3.2 as the paper runs it: B randomised and re-sorted every round,
+    A fixed.  Per-round totals, observed and tails equal (1) the oracle with
+    the shuffled set's table built from B and the sorted arrays from A, and
+    (2) the fixed-reference Monte-Carlo path with A as the reference and B as
+    the queries (no per-round sort); uneven batches of rounds."""
+    note("case: paper orientation batch=%d" % batch)
+    lengths, A, B = datagen.w2_sets(seed=6, n_a=30_000, n_b=3_000)
+    a_s, a_e = oracle.project(lengths, A.chrom, A.start, A.end)
+    b_s, b_e = oracle.project(lengths, B.chrom, B.start, B.end)
+    s0, s1 = 3, 23
+    exp = oracle.mc_totals(np.sort(a_s), np.sort(a_e), oracle.mc_prepare(lengths, b_s, b_e), 11, s0, s1, threads=8)
+    obs = oracle.counter(a_s, a_e, b_s, b_e)[1]
+    mc = bits.bits_mc_resort(up(a_s), up(a_e), up(b_s), up(b_e), lengths, 11, s0, s1, batch=batch)
+    assert np.array_equal(down(mc.totals), exp)
+    assert int(down(mc.observed)[0]) == obs
+    assert (int(down(mc.n_ge)[0]), int(down(mc.n_le)[0])) == oracle.mc_tail(exp, obs)
+    ref_a = bits.bits_sort_ref(up(a_s), up(a_e), learned=True, train={"epochs": 10})
+    swapped = bits.bits_mc_pvalue(ref_a, up(b_s), up(b_e), lengths, 11, s0, s1)
+    assert np.array_equal(down(swapped.totals), exp) and int(down(swapped.observed)[0]) == obs
+
+
+def test_paper_orientation_interval_outside_chromosome():
+    note("case: paper orientation, bad interval")
+    lengths = np.array([1000, 2000], np.uint32)
+    b_s = np.array([10, 990, 1500, 2500], np.uint32)     # interval 1 crosses the end of chromosome 0
+    b_e = np.array([20, 1010, 1600, 2600], np.uint32)
+    a_s = np.arange(0, 3000, 37).astype(np.uint32)
+    a_e = a_s + np.uint32(30)
+    st = torch.zeros(1, dtype=torch.uint32, device=DEV)
+    mc = bits.bits_mc_resort(up(a_s), up(a_e), up(b_s), up(b_e), lengths, 5, 0, 9, batch=4, status=st)
+    assert int(down(st)[0]) & bits.BITS_FLAG_CHROM
+    keep = np.array([True, False, True, True])
+    # the oracle's placements of all four intervals (counter g = 4 s + j; the bad
+    # one gets a dummy table entry and is then dropped), counted against A
+    off, span, ln = oracle.mc_prepare(lengths, b_s[keep], b_e[keep])
+    off4 = np.array([off[0], 0, off[1], off[2]], np.uint32)
+    span4 = np.array([span[0], 1, span[1], span[2]], np.uint32)
+    len4 = np.array([ln[0], 1, ln[1], ln[2]], np.uint32)
+    t = down(mc.totals)
+    for s in range(9):
+        st_ = oracle.mc_placements(5, s, off4, span4)[keep]
+        en_ = st_ + len4[keep] - np.uint32(1)
+        assert int(t[s]) == oracle.counter(a_s, a_e, st_, en_)[1], s
+    assert int(down(mc.observed)[0]) == oracle.counter(a_s, a_e, b_s[keep], b_e[keep])[1]
