@@ -116,6 +116,9 @@ __device__ __forceinline__ uint32_t count_lt4(u32x4 v, uint32_t x) {
     return (v.x < x ? 1u : 0u) + (v.y < x ? 1u : 0u) + (v.z < x ? 1u : 0u) + (v.w < x ? 1u : 0u);
 }
 
+#ifndef BITS_QUAD_SHFL
+#define BITS_QUAD_SHFL 0
+#endif
 #ifndef BITS_PROBE_LANES
 #define BITS_PROBE_LANES 8
 #endif
@@ -244,8 +247,13 @@ __device__ __forceinline__ void quad_leaves(const bits_rmi_model* __restrict__ r
             const float w2[4] = {h2f(B[pass].z & 0xFFFFu), h2f(B[pass].z >> 16), h2f(B[pass].w & 0xFFFFu),
                                  h2f(B[pass].w >> 16)};
             float t = rmi_quad_partial(w1, b1, w2, u);
+#if BITS_QUAD_SHFL
+            t += __shfl_xor(t, 1);   // s0+s1, s2+s3
+            t += __shfl_xor(t, 2);   // (s0+s1)+(s2+s3)
+#else
             t += __uint_as_float(dpp_quad<0xB1>(__float_as_uint(t)));   // s0+s1, s2+s3
             t += __uint_as_float(dpp_quad<0x4E>(__float_as_uint(t)));   // (s0+s1)+(s2+s3)
+#endif
             // lane 0: {kmin, kmax}; 1: {rlo, cnt}; 2: y = b2 + sum; 3: err
             uint32_t* res = scr + c * kLeafScr + 2 * kWave + 6 * owner;
             if (q < 2)
@@ -263,6 +271,14 @@ __device__ __forceinline__ void quad_leaves(const bits_rmi_model* __restrict__ r
 // ------------------------------------------------------------------ ICount
 // first = #{B_S <= a.end} = #{B_S < a.end + 1}; last = #{B_E < a.start};
 // count = first - last (Sec. 2.1).  a.end == 2^32-1 means first = |B|.
+//
+// A lane without a query (past the end of its tile or round, or a query
+// left out) still runs the wave-cooperative searches with the interval
+// [0, kIdleEnd]: both search keys are then 0, below every key routed to a
+// leaf, so the learned searches resolve it from the leaf header without a
+// single probe.  (An idle [0, 0] would search B_S for 1, which a reference
+// with many intervals starting at 0 turns into a fallback bisection.)
+constexpr uint32_t kIdleEnd = 0xFFFFFFFFu;
 
 // Bisection probes kept in L2 on the plain path: the first few probes of a
 // bucket are shared by every query landing in it.
@@ -611,7 +627,7 @@ BITS_SEARCH_KERNEL k_count(SearchArgs sa, const uint32_t* __restrict__ a_start,
             const uint64_t i = t * tile + (uint64_t)q * blockDim.x + threadIdx.x;
             valid[q] = i < na;
             as[q] = valid[q] ? a_start[i] : 0u;
-            ae[q] = valid[q] ? a_end[i] : 0u;
+            ae[q] = valid[q] ? a_end[i] : kIdleEnd;
             if (as[q] > ae[q]) {
                 bad = 1;
                 valid[q] = false;
@@ -663,7 +679,7 @@ BITS_SEARCH_KERNEL k_decide(SearchArgs sa, const uint32_t* __restrict__ a_start,
             const uint64_t i = t * tile + (uint64_t)q * blockDim.x + threadIdx.x;
             valid[q] = i < na;
             as[q] = valid[q] ? a_start[i] : 0u;
-            ae[q] = valid[q] ? a_end[i] : 0u;
+            ae[q] = valid[q] ? a_end[i] : kIdleEnd;
             if (as[q] > ae[q]) {
                 bad = 1;
                 valid[q] = false;
@@ -750,7 +766,7 @@ BITS_SEARCH_KERNEL k_mc(SearchArgs sa, const uint32_t* __restrict__ a_start, con
             valid[q] = qs[q] != 0u;
             if (OBSERVED) {
                 qo[q] = valid[q] ? a_start[qi[q]] : 0u;
-                ql[q] = valid[q] ? a_end[qi[q]] : 0u;
+                ql[q] = valid[q] ? a_end[qi[q]] : kIdleEnd;
             } else {
                 qo[q] = valid[q] ? off[pos] : 0u;
                 ql[q] = valid[q] ? len[pos] : 1u;
@@ -772,7 +788,7 @@ BITS_SEARCH_KERNEL k_mc(SearchArgs sa, const uint32_t* __restrict__ a_start, con
                     const uint64_t u = ((uint64_t)c1 << 32) | c0;
                     const uint32_t local = (uint32_t)__umul64hi(u, (uint64_t)qs[q]);
                     as[q] = valid[q] ? qo[q] + local : 0u;
-                    ae[q] = valid[q] ? as[q] + ql[q] - 1u : 0u;
+                    ae[q] = valid[q] ? as[q] + ql[q] - 1u : kIdleEnd;
                 }
             }
             icount_mc<QPL, LEARNED>(sa, lds, as, ae, cnt);
@@ -784,6 +800,164 @@ BITS_SEARCH_KERNEL k_mc(SearchArgs sa, const uint32_t* __restrict__ a_start, con
         }
         __syncthreads();
         for (uint32_t k = threadIdx.x; k < (uint32_t)(se - sb); k += blockDim.x) {
+            const unsigned long long v = acc[k];
+            if (v) atomicAdd(totals + sb + k, v);
+            acc[k] = 0ull;
+        }
+        __syncthreads();
+    }
+}
+
+// Learned Monte-Carlo with placements sorted inside the work item.  An item
+// (tile of blockDim/8 table positions, chunk of <= kMaxChunk shuffles)
+// generates all its placements, counting-sorts them by start into
+// kSortBuckets buckets over the tile's start range in LDS, and searches them
+// in that order, so that lanes of a wave share leaf records and often head
+// windows: the searches then take fewer L1/L2 requests, the resource that
+// bounds the unsorted kernel.  Placements are made twice (histogram, then
+// scatter) rather than staged unsorted, to fit LDS.  Totals are sums, so
+// the order does not change them.  The placements (start, and query | shuffle
+// << 8 in 16 bits) live in dynamic LDS after the per-wave probe scratch.
+#ifndef BITS_MC_SORTED
+#define BITS_MC_SORTED 1
+#endif
+constexpr uint32_t kSortBuckets = 1024;
+constexpr uint32_t kSortMaxTileQ = 128;
+constexpr uint32_t kSortQBits = 8;
+__host__ __device__ constexpr uint32_t sort_tile_q(uint32_t block) { return block / 8u; }
+__host__ __device__ constexpr size_t sort_lds_bytes(uint32_t block) {
+    return (size_t)(block / kWave) * probe_scratch_words(1) * 4u + (size_t)sort_tile_q(block) * kMaxChunk * 6u;
+}
+static_assert((kMaxChunk << kSortQBits) <= 65536, "sort meta");
+
+// Start of the placement of a query with legal-start count span > 0.
+__device__ __forceinline__ uint32_t mc_place(uint64_t g, uint32_t k0, uint32_t k1, uint32_t off, uint32_t span) {
+    uint32_t c0 = (uint32_t)g, c1 = (uint32_t)(g >> 32), c2 = 0u, c3 = 0u;
+    philox4x32_10(c0, c1, c2, c3, k0, k1);
+    const uint64_t u = ((uint64_t)c1 << 32) | c0;
+    return off + (uint32_t)__umul64hi(u, (uint64_t)span);
+}
+
+// In-place exclusive scan of kSortBuckets counters by the whole workgroup;
+// returns the total.
+__device__ __forceinline__ uint32_t block_scan_buckets(uint32_t* h, uint32_t* wsum) {
+    const uint32_t per = kSortBuckets / blockDim.x;            // 1, 2 or 4 (blocks of 1024, 512, 256)
+    const uint32_t b0 = threadIdx.x * per;
+    uint32_t v[4] = {0u, 0u, 0u, 0u};
+    uint32_t mine = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        if (k < per) v[k] = h[b0 + k];
+        mine += v[k];
+    }
+    const uint32_t lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint32_t x = mine;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    if (lane == kWave - 1) wsum[w] = x;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (uint32_t k = 0; k < blockDim.x / kWave; ++k) {
+        if (k < w) pre += wsum[k];
+        tot += wsum[k];
+    }
+    pre += x - mine;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        if (k < per) h[b0 + k] = pre;
+        pre += v[k];
+    }
+    __syncthreads();
+    return tot;
+}
+
+BITS_SEARCH_KERNEL k_mc_sorted(SearchArgs sa, const uint32_t* __restrict__ off, const uint32_t* __restrict__ span,
+                               const uint32_t* __restrict__ len, const uint32_t* __restrict__ idx, uint64_t na,
+                               uint64_t seed, uint64_t s0, uint64_t nshuf, uint64_t tiles, uint32_t chunk,
+                               unsigned long long* __restrict__ totals) {
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t hist[kSortBuckets];
+    __shared__ uint32_t t_off[kSortMaxTileQ], t_span[kSortMaxTileQ], t_len[kSortMaxTileQ], t_idx[kSortMaxTileQ];
+    __shared__ unsigned long long acc[kMaxChunk];
+    __shared__ uint32_t wsum[16], lo_key, hi_key;
+    const uint32_t tile_q = sort_tile_q(blockDim.x);           // 32, 64 or 128
+    uint32_t* scr = lds + (threadIdx.x / kWave) * probe_scratch_words(1);
+    uint32_t* p_start = lds + (blockDim.x / kWave) * probe_scratch_words(1);
+    uint16_t* p_meta = reinterpret_cast<uint16_t*>(p_start + tile_q * kMaxChunk);
+    for (uint32_t k = threadIdx.x; k < kMaxChunk; k += blockDim.x) acc[k] = 0ull;
+    const uint64_t nchunks = (nshuf + chunk - 1) / chunk;
+    const uint32_t ng = (gridDim.x >= kXcds && tiles >= kXcds) ? kXcds : 1u;
+    const uint32_t grp = blockIdx.x % ng, slot = blockIdx.x / ng;
+    const uint32_t nslots = (gridDim.x - grp + ng - 1) / ng;
+    const uint64_t t_lo = tiles * grp / ng, gtiles = tiles * (grp + 1) / ng - t_lo;
+    const uint64_t nitems = gtiles * nchunks;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    __syncthreads();
+    for (uint64_t it = slot; it < nitems; it += nslots) {
+        const uint64_t kc = it / gtiles;
+        const uint64_t t = t_lo + (it - kc * gtiles);
+        const uint64_t sb = kc * chunk;
+        const uint32_t nsh = (uint32_t)min((uint64_t)chunk, nshuf - sb);
+        // 1. the tile's table and its start range
+        if (threadIdx.x == 0) {
+            lo_key = 0xFFFFFFFFu;
+            hi_key = 0u;
+        }
+        for (uint32_t k = threadIdx.x; k < kSortBuckets; k += blockDim.x) hist[k] = 0u;
+        __syncthreads();
+        if (threadIdx.x < tile_q) {
+            const uint64_t pos = t * tile_q + threadIdx.x;
+            const bool in = pos < na;
+            const uint32_t sp = in ? span[pos] : 0u;
+            t_span[threadIdx.x] = sp;
+            t_off[threadIdx.x] = in ? off[pos] : 0u;
+            t_len[threadIdx.x] = in ? len[pos] : 1u;
+            t_idx[threadIdx.x] = in ? idx[pos] : 0u;
+            if (sp) {
+                atomicMin(&lo_key, t_off[threadIdx.x]);
+                atomicMax(&hi_key, t_off[threadIdx.x] + (sp - 1u));
+            }
+        }
+        __syncthreads();
+        const uint32_t lo = lo_key;
+        const uint32_t range = hi_key >= lo ? hi_key - lo : 0u;
+        const uint32_t bits = range ? 32u - __clz(range) : 0u;
+        const uint32_t shift = bits > 10u ? bits - 10u : 0u;   // (range >> shift) < 1024
+        const uint32_t P = tile_q * nsh;
+        // 2. histogram of the placements' buckets
+        for (uint32_t p = threadIdx.x; p < P; p += blockDim.x) {
+            const uint32_t q = p & (tile_q - 1), sh = p / tile_q;
+            if (!t_span[q]) continue;
+            const uint32_t st = mc_place((s0 + sb + sh) * na + t_idx[q], k0, k1, t_off[q], t_span[q]);
+            atomicAdd(&hist[(st - lo) >> shift], 1u);
+        }
+        __syncthreads();
+        const uint32_t nvalid = block_scan_buckets(hist, wsum);
+        // 3. the same placements again, scattered into bucket order
+        for (uint32_t p = threadIdx.x; p < P; p += blockDim.x) {
+            const uint32_t q = p & (tile_q - 1), sh = p / tile_q;
+            if (!t_span[q]) continue;
+            const uint32_t st = mc_place((s0 + sb + sh) * na + t_idx[q], k0, k1, t_off[q], t_span[q]);
+            const uint32_t at = atomicAdd(&hist[(st - lo) >> shift], 1u);
+            p_start[at] = st;
+            p_meta[at] = (uint16_t)(q | (sh << kSortQBits));
+        }
+        __syncthreads();
+        // 4. the searches, in start order (every lane runs every round: the probes are wave-cooperative)
+        for (uint32_t r0 = 0; r0 < nvalid; r0 += blockDim.x) {
+            const uint32_t p = r0 + threadIdx.x;
+            const bool valid = p < nvalid;
+            const uint32_t st = valid ? p_start[p] : 0u;
+            const uint32_t m = valid ? p_meta[p] : 0u;
+            uint32_t as[1] = {st}, ae[1] = {valid ? st + t_len[m & (tile_q - 1)] - 1u : kIdleEnd}, cnt[1], fst[1];
+            icount_heads<1>(sa, scr, as, ae, cnt, fst);
+            if (valid && cnt[0]) atomicAdd(&acc[m >> kSortQBits], (unsigned long long)cnt[0]);
+        }
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < nsh; k += blockDim.x) {
             const unsigned long long v = acc[k];
             if (v) atomicAdd(totals + sb + k, v);
             acc[k] = 0ull;
@@ -937,7 +1111,7 @@ BITS_SEARCH_KERNEL k_count_rounds(SearchArgs sa0, const uint32_t* __restrict__ S
             const uint64_t i = t * tile + (uint64_t)q * blockDim.x + threadIdx.x;
             valid[q] = i < na;
             as[q] = valid[q] ? a_start[i] : 0u;
-            ae[q] = valid[q] ? a_end[i] : 0u;
+            ae[q] = valid[q] ? a_end[i] : kIdleEnd;
             if (as[q] > ae[q]) {
                 bad = 1;
                 valid[q] = false;
@@ -1087,7 +1261,7 @@ __global__ void __launch_bounds__(1024)
             const uint64_t i = (uint64_t)item.begin + k;
             valid[q] = k < item.count;
             as[q] = valid[q] ? Q.as[i] : 0u;
-            ae[q] = valid[q] ? Q.ae[i] : 0u;
+            ae[q] = valid[q] ? Q.ae[i] : kIdleEnd;
             if (as[q] > ae[q]) {
                 bad = 1;
                 valid[q] = false;
@@ -1293,7 +1467,17 @@ static hipError_t launch_mc_t(const SearchArgs& sa, const LaunchCfg& cfg, const 
         hipLaunchKernelGGL((k_mc<QPL, LEARNED, true>), dim3(go), dim3(cfg.block), lds, s, sa, as, ae, tab.off,
                            tab.span, tab.len, tab.idx, na, seed, s0, (uint64_t)1, tps, 1u, observed);
     }
-    if (nshuf) {
+    // the sorted kernel when its LDS (dynamic + ~7 KB static) fits the device's per-workgroup limit
+    if (nshuf && LEARNED && BITS_MC_SORTED && sort_lds_bytes(cfg.block) + 8192 <= device_lds_per_block()) {
+        const size_t lds1 = sort_lds_bytes(cfg.block);
+        const uint64_t tq = (na + sort_tile_q(cfg.block) - 1) / sort_tile_q(cfg.block);
+        const void* km = (const void*)k_mc_sorted;
+        const uint32_t gm = persistent_grid(km, cfg, lds1, nshuf * tq);
+        uint32_t chunk = kMaxChunk;
+        while (chunk > 1 && tq * ((nshuf + chunk - 1) / chunk) < 8ull * gm) chunk >>= 1;
+        hipLaunchKernelGGL(k_mc_sorted, dim3(gm), dim3(cfg.block), lds1, s, sa, tab.off, tab.span, tab.len, tab.idx,
+                           na, seed, s0, nshuf, tq, chunk, totals);
+    } else if (nshuf) {
         const void* km = (const void*)k_mc<QPL, LEARNED, false>;
         const uint32_t gm = persistent_grid(km, cfg, lds, nshuf * tps);
         // shuffles per work item: as many as keep >= 8 items per workgroup
