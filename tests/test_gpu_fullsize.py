@@ -18,7 +18,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 from paper_1208_3407_amd import bits  # noqa: E402
 
-from bench import RECORDED_LEARNED, RECORDED_PLAIN  # noqa: E402  (bench's launch shapes)
+from bench import RECORDED_LEARNED, RECORDED_MC, RECORDED_PLAIN  # noqa: E402  (bench's launch shapes)
 
 DEV = torch.device("cuda", 0)
 THREADS = 16
@@ -73,7 +73,7 @@ def test_w2_full_monte_carlo_sampled_shuffles():
     b_s, b_e = proj(lengths, B)
     ref = bits.bits_sort_ref(b_s, b_e, learned=True)
     N = 10_000
-    mc = bits.bits_mc_pvalue(ref, a_s, a_e, lengths, datagen.MC_SEED, 0, N, launch=RECORDED_LEARNED)
+    mc = bits.bits_mc_pvalue(ref, a_s, a_e, lengths, datagen.MC_SEED, 0, N, launch=RECORDED_MC)
     T = down(mc.totals).copy()
     obs, ge, le = int(down(mc.observed)[0]), int(down(mc.n_ge)[0]), int(down(mc.n_le)[0])
     mcp = bits.bits_mc_pvalue(ref, a_s, a_e, lengths, datagen.MC_SEED, 0, N, launch=RECORDED_PLAIN)
@@ -138,7 +138,7 @@ def test_w4_full_learned_vs_plain_and_sampled():
     _, total = oracle.count_sorted(sbs, sbe, oa_s, oa_e, threads=THREADS, per_query=False)
     assert int(down(t_learn)[0]) == total and int(down(t_plain)[0]) == total
     nmc = 1_000_000
-    mc = bits.bits_mc_pvalue(ref, a_s[:nmc], a_e[:nmc], lengths, datagen.MC_SEED, 0, 1000, launch=RECORDED_LEARNED)
+    mc = bits.bits_mc_pvalue(ref, a_s[:nmc], a_e[:nmc], lengths, datagen.MC_SEED, 0, 1000, launch=RECORDED_MC)
     T = down(mc.totals).copy()
     prep = oracle.mc_prepare(lengths, oa_s[:nmc], oa_e[:nmc])
     for s in (0, 1, 500, 999):
