@@ -149,7 +149,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--epochs", type=int, default=80)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the recorded best launch shapes instead of timing candidates")
     ap.add_argument("--copy-calibration", action="store_true",
