@@ -372,3 +372,54 @@ def test_broken_model_stays_exact(b2):
     assert int(down(mc.observed)[0]) == exp_t
     assert bits.bits_rmi_info(ref)["fallbacks"] > fb0
     assert bits.bits_get_status(ref) == 0
+
+
+def _mc_expected_with_left_out(lengths, a_s, a_e, ok, b_s, b_e, seed, s0, s1):
+    """Per-shuffle totals by the oracle when the queries with ok = False are
+    left out: placements of all queries from the oracle's stream (counter
+    s * na + i; left-out queries get a dummy table entry), then a plain count
+    of the placed kept queries."""
+    off, span, ln = oracle.mc_prepare(lengths, a_s[ok], a_e[ok])
+    na = len(a_s)
+    off_all, span_all, len_all = np.zeros(na, np.uint32), np.ones(na, np.uint32), np.ones(na, np.uint32)
+    off_all[ok], span_all[ok], len_all[ok] = off, span, ln
+    out = []
+    for s in range(s0, s1):
+        st = oracle.mc_placements(seed, s, off_all, span_all)[ok]
+        out.append(oracle.counter(st, st + len_all[ok] - np.uint32(1), b_s, b_e)[1])
+    return np.array(out, dtype=np.uint64)
+
+
+@pytest.mark.parametrize("block", [256, 512, 1024])
+def test_monte_carlo_sorted_items(block):
+    """The learned Monte-Carlo kernel sorts each item's placements (tile of
+    block/8 queries x up to 64 shuffles) before searching.  Shuffle counts that
+    leave partial chunks and idle lanes (1, 7, 70), tiles that straddle
+    chromosomes, and a run of queries outside their chromosome long enough to
+    fill whole tiles: totals must still equal the oracle's."""
+    note("case: MC sorted items block=%d" % block)
+    r = np.random.default_rng(block)
+    lengths = np.array([300_000, 50_000, 1_000, 200_000, 7_000], np.uint32)
+    off = oracle.genome_offsets(lengths).astype(np.int64)
+    na, nb = 3_000, 20_000
+
+    def placed(n, maxlen):
+        c = r.integers(0, len(lengths), size=n)
+        L = np.minimum(r.integers(1, maxlen + 1, size=n), lengths[c].astype(np.int64))
+        s = r.integers(0, lengths[c].astype(np.int64) - L + 1)
+        return (off[c] + s).astype(np.uint32), (off[c] + s + L - 1).astype(np.uint32)
+    a_s, a_e = placed(na, 400)
+    b_s, b_e = placed(nb, 300)
+    # queries 100..399 cross the end of chromosome 1 (left out, flagged)
+    a_s[100:400] = np.uint32(off[2] - 10)
+    a_e[100:400] = np.uint32(off[2] + 10)
+    ok = np.ones(na, bool)
+    ok[100:400] = False
+    ref = bits.bits_sort_ref(up(b_s), up(b_e), learned=True, train={"epochs": 20})
+    for s0, s1 in ((0, 1), (5, 12), (3, 73)):
+        exp = _mc_expected_with_left_out(lengths, a_s, a_e, ok, b_s, b_e, 9, s0, s1)
+        mc = bits.bits_mc_pvalue(ref, up(a_s), up(a_e), lengths, 9, s0, s1,
+                                 launch={"path": bits.BITS_PATH_LEARNED, "block": block, "qpl": 1})
+        assert np.array_equal(down(mc.totals), exp), (s0, s1)
+        assert int(down(mc.observed)[0]) == oracle.counter(a_s[ok], a_e[ok], b_s, b_e)[1]
+    assert bits.bits_get_status(ref) & bits.BITS_FLAG_CHROM
