@@ -821,12 +821,16 @@ BITS_SEARCH_KERNEL k_mc(SearchArgs sa, const uint32_t* __restrict__ a_start, con
 #ifndef BITS_MC_SORTED
 #define BITS_MC_SORTED 1
 #endif
+#ifndef BITS_MC_SORTED_QPL
+#define BITS_MC_SORTED_QPL 1
+#endif
+constexpr int kSortQpl = BITS_MC_SORTED_QPL;   // placements per lane per search round
 constexpr uint32_t kSortBuckets = 1024;
 constexpr uint32_t kSortMaxTileQ = 128;
 constexpr uint32_t kSortQBits = 8;
 __host__ __device__ constexpr uint32_t sort_tile_q(uint32_t block) { return block / 8u; }
 __host__ __device__ constexpr size_t sort_lds_bytes(uint32_t block) {
-    return (size_t)(block / kWave) * probe_scratch_words(1) * 4u + (size_t)sort_tile_q(block) * kMaxChunk * 6u;
+    return (size_t)(block / kWave) * probe_scratch_words(kSortQpl) * 4u + (size_t)sort_tile_q(block) * kMaxChunk * 6u;
 }
 static_assert((kMaxChunk << kSortQBits) <= 65536, "sort meta");
 
@@ -884,8 +888,8 @@ BITS_SEARCH_KERNEL k_mc_sorted(SearchArgs sa, const uint32_t* __restrict__ off, 
     __shared__ unsigned long long acc[kMaxChunk];
     __shared__ uint32_t wsum[16], lo_key, hi_key;
     const uint32_t tile_q = sort_tile_q(blockDim.x);           // 32, 64 or 128
-    uint32_t* scr = lds + (threadIdx.x / kWave) * probe_scratch_words(1);
-    uint32_t* p_start = lds + (blockDim.x / kWave) * probe_scratch_words(1);
+    uint32_t* scr = lds + (threadIdx.x / kWave) * probe_scratch_words(kSortQpl);
+    uint32_t* p_start = lds + (blockDim.x / kWave) * probe_scratch_words(kSortQpl);
     uint16_t* p_meta = reinterpret_cast<uint16_t*>(p_start + tile_q * kMaxChunk);
     for (uint32_t k = threadIdx.x; k < kMaxChunk; k += blockDim.x) acc[k] = 0ull;
     const uint64_t nchunks = (nshuf + chunk - 1) / chunk;
@@ -947,14 +951,21 @@ BITS_SEARCH_KERNEL k_mc_sorted(SearchArgs sa, const uint32_t* __restrict__ off, 
         }
         __syncthreads();
         // 4. the searches, in start order (every lane runs every round: the probes are wave-cooperative)
-        for (uint32_t r0 = 0; r0 < nvalid; r0 += blockDim.x) {
-            const uint32_t p = r0 + threadIdx.x;
-            const bool valid = p < nvalid;
-            const uint32_t st = valid ? p_start[p] : 0u;
-            const uint32_t m = valid ? p_meta[p] : 0u;
-            uint32_t as[1] = {st}, ae[1] = {valid ? st + t_len[m & (tile_q - 1)] - 1u : kIdleEnd}, cnt[1], fst[1];
-            icount_heads<1>(sa, scr, as, ae, cnt, fst);
-            if (valid && cnt[0]) atomicAdd(&acc[m >> kSortQBits], (unsigned long long)cnt[0]);
+        for (uint32_t r0 = 0; r0 < nvalid; r0 += kSortQpl * blockDim.x) {
+            uint32_t as[kSortQpl], ae[kSortQpl], cnt[kSortQpl], fst[kSortQpl], m[kSortQpl];
+            bool valid[kSortQpl];
+#pragma unroll
+            for (uint32_t q = 0; q < kSortQpl; ++q) {
+                const uint32_t p = r0 + q * blockDim.x + threadIdx.x;
+                valid[q] = p < nvalid;
+                as[q] = valid[q] ? p_start[p] : 0u;
+                m[q] = valid[q] ? p_meta[p] : 0u;
+                ae[q] = valid[q] ? as[q] + t_len[m[q] & (tile_q - 1)] - 1u : kIdleEnd;
+            }
+            icount_heads<kSortQpl>(sa, scr, as, ae, cnt, fst);
+#pragma unroll
+            for (uint32_t q = 0; q < kSortQpl; ++q)
+                if (valid[q] && cnt[q]) atomicAdd(&acc[m[q] >> kSortQBits], (unsigned long long)cnt[q]);
         }
         __syncthreads();
         for (uint32_t k = threadIdx.x; k < nsh; k += blockDim.x) {
