@@ -54,6 +54,7 @@ typedef enum bits_status {
                                      count, or the pair buffer was too small */
 
 #define BITS_MAX_CHROM   256u     /* chromosomes per genome for projection / Monte-Carlo */
+#define BITS_MC_BIN_MAX_BATCH 1024u /* shuffles per pass of bits_mc_binned */
 #define BITS_MAX_DEPTH   13u      /* Eytzinger top-tree levels held in LDS */
 #define BITS_RMI_LEAVES  4096u    /* leaf models per learned index */
 #define BITS_RMI_HIDDEN  16u      /* hidden ReLU units per leaf model */
@@ -282,6 +283,41 @@ int bits_mc_pvalue(const bits_ref *ref, const uint32_t *d_a_start, const uint32_
                    uint64_t s0, uint64_t s1, void *d_ws, size_t ws_bytes, uint64_t *d_totals,
                    uint64_t *d_observed, uint64_t *d_n_ge, uint64_t *d_n_le,
                    const bits_launch *launch, void *stream);
+
+/* Workspace bytes of bits_mc_binned for na queries (na < 2^32) against a
+ * reference of n intervals on the genome chrom_len[n_chrom], with `batch`
+ * shuffles per pass (1 <= batch <= BITS_MC_BIN_MAX_BATCH): the query table
+ * of bits_mc_workspace; 28 bytes per cell of the genome (cells of 2^S bp,
+ * S >= 10 the least that leaves at most 8192 cells in every chromosome);
+ * 16 + 16 * batch bytes per region (at most n_chrom + 2n / 8192 regions);
+ * and 8 * batch * na bytes of placement records.  BITS_E_CHROM if the
+ * genome is 2^32 bp or more. */
+int bits_mc_binned_workspace(uint64_t na, uint64_t n, const uint32_t *chrom_len, uint32_t n_chrom,
+                             uint32_t batch, size_t *bytes);
+
+/* The Monte-Carlo loop of bits_mc_pvalue (same shuffles, same Philox
+ * stream, same outputs bit for bit), ordered by region of the genome
+ * rather than by query.  Each chromosome is cut into cells; a region is a
+ * run of cells holding about 8192 keys of B_S and B_E together.  Per pass
+ * of `batch` shuffles:
+ *   1. binning: the placements of every (shuffle, chromosome) are made,
+ *      counted per region, made again and written as {start, end} records
+ *      in region order (8 bytes per placement into d_ws);
+ *   2. search: one workgroup per region stages the region's slices of B_S
+ *      and B_E in LDS and counts every placement of the pass that starts in
+ *      the region by two bisections there (Algorithm 1); ends past the
+ *      region continue in HBM;
+ *   3. the per-region sums are added to d_totals.
+ * The total of each shuffle is a sum over its placements, so this order
+ * gives the same totals.  The observed total uses the reference's own
+ * search (launch: its path and shape; NULL = defaults).  Needs no learned
+ * index.  Arguments, outputs and flags as bits_mc_pvalue; d_ws of
+ * bits_mc_binned_workspace(na, ref->n, chrom_len, n_chrom, batch) bytes.
+ * BITS_E_ARG for batch outside [1, BITS_MC_BIN_MAX_BATCH]. */
+int bits_mc_binned(const bits_ref *ref, const uint32_t *d_a_start, const uint32_t *d_a_end, uint64_t na,
+                   const uint32_t *chrom_len, uint32_t n_chrom, uint64_t seed, uint64_t s0, uint64_t s1,
+                   uint32_t batch, void *d_ws, size_t ws_bytes, uint64_t *d_totals, uint64_t *d_observed,
+                   uint64_t *d_n_ge, uint64_t *d_n_le, const bits_launch *launch, void *stream);
 
 /* Workspace bytes of bits_mc_resort for |B| = nb and `batch` rounds per
  * sort launch (1 <= batch <= 4096): 16 bytes per interval of B, 16 bytes per

@@ -104,6 +104,9 @@ def _load():
         "bits_scan_workspace": ([_u64, P(_sz)], ctypes.c_int),
         "bits_scan_counts": ([_vp, _u64, _vp, _vp, _sz, _vp], ctypes.c_int),
         "bits_mc_resort_workspace": ([_u64, _u32, P(_sz)], ctypes.c_int),
+        "bits_mc_binned_workspace": ([_u64, _u64, P(_u32), _u32, _u32, P(_sz)], ctypes.c_int),
+        "bits_mc_binned": ([P(bits_ref), _vp, _vp, _u64, P(_u32), _u32, _u64, _u64, _u64, _u32, _vp, _sz, _vp, _vp,
+                            _vp, _vp, P(bits_launch), _vp], ctypes.c_int),
         "bits_mc_resort": ([_vp, _vp, _u64, _vp, _vp, _u64, P(_u32), _u32, _u64, _u64, _u64, _u32, _vp, _sz, _vp,
                             _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
         "bits_pvalue_lower": ([_u64, _u64], ctypes.c_double),
@@ -403,6 +406,37 @@ def bits_mc_pvalue(ref: Ref, a_start, a_end, chrom_len, seed: int, s0: int, s1: 
                                int(s1), _ptr(workspace), workspace.numel(), _ptr(out.totals),
                                ctypes.c_void_p(out.observed.data_ptr()), ctypes.c_void_p(out.n_ge.data_ptr()),
                                ctypes.c_void_p(out.n_le.data_ptr()), _lp(launch), _stream(stream)), "bits_mc_pvalue")
+    out._keepalive = workspace
+    return out
+
+
+def bits_mc_binned_workspace(na: int, n: int, chrom_len, batch: int) -> int:
+    out = _sz(0)
+    cl = _host_u32(chrom_len)
+    _check(_lib.bits_mc_binned_workspace(int(na), int(n), cl, len(cl), int(batch), ctypes.byref(out)),
+           "bits_mc_binned_workspace")
+    return int(out.value)
+
+
+def bits_mc_binned(ref: Ref, a_start, a_end, chrom_len, seed: int, s0: int, s1: int, batch: int = 256,
+                   launch=None, workspace: Optional[torch.Tensor] = None, out: Optional[MCResult] = None,
+                   stream=None) -> MCResult:
+    """Monte-Carlo shuffles [s0, s1) of A against the reference, binned by genome region and
+    counted in LDS, `batch` shuffles per pass; same totals as bits_mc_pvalue."""
+    dev = _device()
+    a_start, a_end = _u32_dev(a_start, "a_start"), _u32_dev(a_end, "a_end")
+    na = a_start.numel()
+    if workspace is None:
+        workspace = _scratch(bits_mc_binned_workspace(na, ref.n, chrom_len, batch), dev)
+    if out is None:
+        out = MCResult(torch.empty(max(s1 - s0, 1), dtype=torch.uint64, device=dev)[:max(s1 - s0, 0)],
+                       torch.empty(1, dtype=torch.uint64, device=dev), torch.empty(1, dtype=torch.uint64, device=dev),
+                       torch.empty(1, dtype=torch.uint64, device=dev))
+    cl = _host_u32(chrom_len)
+    _check(_lib.bits_mc_binned(ctypes.byref(ref.c), _ptr(a_start), _ptr(a_end), na, cl, len(cl), int(seed), int(s0),
+                               int(s1), int(batch), _ptr(workspace), workspace.numel(), _ptr(out.totals),
+                               ctypes.c_void_p(out.observed.data_ptr()), ctypes.c_void_p(out.n_ge.data_ptr()),
+                               ctypes.c_void_p(out.n_le.data_ptr()), _lp(launch), _stream(stream)), "bits_mc_binned")
     out._keepalive = workspace
     return out
 

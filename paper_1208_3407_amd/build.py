@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbits.so")
-SOURCES = ["api.hip", "search.hip", "sort.hip", "rmi.hip", "enum.hip"]
+SOURCES = ["api.hip", "search.hip", "sort.hip", "rmi.hip", "enum.hip", "binned.hip"]
 ARCH = os.environ.get("BITS_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Wall", "-Wno-unused-function",

@@ -407,6 +407,113 @@ int bits_mc_pvalue(const bits_ref* ref, const uint32_t* d_a_start, const uint32_
     return BITS_OK;
 }
 
+// ---------------------------------------------------------------- Monte-Carlo binned by region
+
+namespace {
+struct BinWsLayout {
+    BinLayout L;
+    size_t table, rs, re, flag, offsets, tiles, cell_region, desc, seg_start, seg_cnt, partial, recs, total;
+};
+
+bool bin_ws_layout(uint64_t na, uint64_t n, const uint32_t* chrom_len, uint32_t n_chrom, uint32_t batch,
+                   BinWsLayout* W) {
+    if (!bin_layout(chrom_len, n_chrom, n, &W->L)) return false;
+    const uint64_t nc = W->L.ncells, nr = W->L.nreg_max;
+    size_t o = 0;
+    W->table = o;
+    o += 4 * align256((size_t)na * sizeof(uint32_t)) + 2 * align256(BITS_MAX_CHROM * sizeof(uint32_t));
+    W->rs = o; o = align256(o + nc * sizeof(uint32_t));
+    W->re = o; o = align256(o + nc * sizeof(uint32_t));
+    W->flag = o; o = align256(o + nc * sizeof(uint32_t));
+    W->offsets = o; o = align256(o + (nc + 1) * sizeof(uint64_t));
+    W->tiles = o; o = align256(o + scan_tiles(nc) * sizeof(uint64_t));
+    W->cell_region = o; o = align256(o + nc * sizeof(uint32_t));
+    W->desc = o; o = align256(o + (nr + 1) * 16);
+    W->seg_start = o; o = align256(o + (size_t)batch * nr * sizeof(uint32_t));
+    W->seg_cnt = o; o = align256(o + (size_t)batch * nr * sizeof(uint32_t));
+    W->partial = o; o = align256(o + (size_t)batch * nr * sizeof(uint64_t));
+    W->recs = o; o = align256(o + (size_t)batch * na * 8);
+    W->total = o;
+    return true;
+}
+}  // namespace
+
+int bits_mc_binned_workspace(uint64_t na, uint64_t n, const uint32_t* chrom_len, uint32_t n_chrom, uint32_t batch,
+                             size_t* bytes) {
+    if (!bytes || !chrom_len || n_chrom == 0 || n_chrom > BITS_MAX_CHROM) return BITS_E_ARG;
+    if (na > 0xFFFFFFFFull || n > 0xFFFFFFFFull || batch == 0 || batch > BITS_MC_BIN_MAX_BATCH) return BITS_E_ARG;
+    BinWsLayout W;
+    if (!bin_ws_layout(na, n, chrom_len, n_chrom, batch, &W)) return BITS_E_CHROM;
+    *bytes = W.total;
+    return BITS_OK;
+}
+
+int bits_mc_binned(const bits_ref* ref, const uint32_t* d_a_start, const uint32_t* d_a_end, uint64_t na,
+                   const uint32_t* chrom_len, uint32_t n_chrom, uint64_t seed, uint64_t s0, uint64_t s1,
+                   uint32_t batch, void* d_ws, size_t ws_bytes, uint64_t* d_totals, uint64_t* d_observed,
+                   uint64_t* d_n_ge, uint64_t* d_n_le, const bits_launch* launch, void* stream) {
+    int rc = check_queries(ref, d_a_start, d_a_end, na);
+    if (rc != BITS_OK) return rc;
+    if (s1 < s0 || !chrom_len || n_chrom == 0 || n_chrom > BITS_MAX_CHROM) return BITS_E_ARG;
+    if (!d_observed || !d_n_ge || !d_n_le || (s1 > s0 && !d_totals)) return BITS_E_ARG;
+    if (batch == 0 || batch > BITS_MC_BIN_MAX_BATCH) return BITS_E_ARG;
+    const uint64_t ns = s1 - s0;
+    if (na > 0xFFFFFFFFull) return BITS_E_ARG;
+    if (na && ns > ~0ull / na) return BITS_E_ARG;   // counter g = s * na + i must not wrap
+    if (na && s1 > (~0ull - na) / na) return BITS_E_ARG;
+    uint64_t g = 0;
+    for (uint32_t c = 0; c < n_chrom; ++c) g += chrom_len[c];
+    if (g > 0xFFFFFFFFull) return BITS_E_CHROM;
+    BinWsLayout W;
+    if (!bin_ws_layout(na, ref->n, chrom_len, n_chrom, batch, &W)) return BITS_E_CHROM;
+    if (na && ref->n && (!d_ws || ws_bytes < W.total)) return BITS_E_WORKSPACE;
+    LaunchCfg cfg;
+    rc = resolve_launch(ref, launch, &cfg);
+    if (rc != BITS_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    auto* totals = (unsigned long long*)d_totals;
+    auto* obs = (unsigned long long*)d_observed;
+    BITS_CHECK_HIP(launch_fill_u64(totals, ns, 0ull, s));
+    BITS_CHECK_HIP(launch_fill_u64(obs, 1, 0ull, s));
+    if (na && ref->n) {
+        char* w = (char*)d_ws;
+        const size_t stride = align256((size_t)na * sizeof(uint32_t));
+        const size_t cstride = align256(BITS_MAX_CHROM * sizeof(uint32_t));
+        McTable tab;
+        tab.off = (uint32_t*)(w + W.table);
+        tab.span = (uint32_t*)(w + W.table + stride);
+        tab.len = (uint32_t*)(w + W.table + 2 * stride);
+        tab.idx = (uint32_t*)(w + W.table + 3 * stride);
+        tab.hist = (uint32_t*)(w + W.table + 4 * stride);
+        tab.cursor = (uint32_t*)(w + W.table + 4 * stride + cstride);
+        BinWs bw;
+        bw.rs = (uint32_t*)(w + W.rs);
+        bw.re = (uint32_t*)(w + W.re);
+        bw.flag = (uint32_t*)(w + W.flag);
+        bw.offsets = (uint64_t*)(w + W.offsets);
+        bw.scan_tiles = (uint64_t*)(w + W.tiles);
+        bw.cell_region = (uint32_t*)(w + W.cell_region);
+        bw.desc = w + W.desc;
+        bw.seg_start = (uint32_t*)(w + W.seg_start);
+        bw.seg_cnt = (uint32_t*)(w + W.seg_cnt);
+        bw.partial = (unsigned long long*)(w + W.partial);
+        bw.recs = w + W.recs;
+        bw.nreg_max = (uint32_t)W.L.nreg_max;
+        BITS_CHECK_HIP(launch_mc_prepare(d_a_start, d_a_end, na, chrom_len, n_chrom, tab, ref->status, s));
+        BITS_CHECK_HIP(launch_mc(make_search_args(ref, cfg), cfg, d_a_start, d_a_end, tab, na, seed, s0, 0, totals,
+                                 obs, s));
+        if (W.L.ncells && ns)   // a genome of length 0 holds no legal placement
+            BITS_CHECK_HIP(launch_bin_regions(chrom_len, n_chrom, ref->bs, ref->be, ref->n, bw, ref->status, s));
+        for (uint64_t sb = s0; W.L.ncells && sb < s1; sb += batch) {
+            const uint32_t nb = (uint32_t)((s1 - sb) < batch ? (s1 - sb) : batch);
+            BITS_CHECK_HIP(launch_bin_batch(chrom_len, n_chrom, tab, na, ref->bs, ref->be, ref->n, seed, sb, nb, bw,
+                                            totals + (sb - s0), s));
+        }
+    }
+    BITS_CHECK_HIP(launch_mc_tail(totals, ns, obs, (unsigned long long*)d_n_ge, (unsigned long long*)d_n_le, s));
+    return BITS_OK;
+}
+
 // ---------------------------------------------------------------- enumeration
 
 namespace {

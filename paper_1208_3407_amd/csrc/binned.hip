@@ -1,0 +1,411 @@
+// Monte-Carlo shuffles binned by genome region (Sec. 3.2) for gfx950.
+//
+// A shuffle's total is a sum over its placements of first - last (Algorithm 1),
+// so the placements may be counted in any order.  This path orders them by
+// region of the genome, so that the slice of B_S and B_E a region needs is
+// read from HBM once per batch of shuffles into LDS and every search runs in
+// LDS, with no per-search memory request:
+//   regions  each chromosome is cut into cells of 2^S bp; a region is a run of
+//            consecutive cells of one chromosome, cut where the merged count of
+//            B_S and B_E keys since the chromosome's start crosses a multiple
+//            of kRegionKeys, so regions follow B's density;
+//   binning  per (shuffle, chromosome): the placements of the chromosome's
+//            queries are made (the Philox stream of the other Monte-Carlo
+//            kernels), counted per region, made again and written, with their
+//            ends, in region order: one segment per (shuffle, region);
+//   search   per region: both slices are staged in LDS (B_S with kMargin keys
+//            past the region's end, for ends that cross it), each placement of
+//            each shuffle of the batch is counted by two bisections in LDS, and
+//            the per-shuffle sums are written out;
+//   reduce   per shuffle: the sums over regions are added to the totals.
+// A region whose slices exceed the LDS capacity (very dense or duplicated
+// keys) is searched in HBM by the same bisections; an end past the staged
+// margin continues by galloping search in HBM.  Both only cost speed.
+#include <algorithm>
+
+#include "bits_internal.hpp"
+
+namespace bits {
+
+namespace {
+
+constexpr uint32_t kMaxCells = 8192;       // cells per chromosome (LDS table of the binning kernel)
+constexpr uint32_t kMinShift = 10;         // cells are at least 1 kbp
+constexpr uint32_t kRegionKeys = 8192;     // merged B_S + B_E keys per region (target)
+constexpr uint32_t kMargin = 256;          // B_S keys staged past a region's end
+constexpr uint32_t kSliceWords = 14336;    // LDS slice capacity of the search kernel (56 KiB)
+constexpr uint32_t kBinThreads = 1024;
+
+// Per-chromosome geometry, passed by value: off[k] = first coordinate of
+// chromosome k (off[n] = genome size), cb[k] = its first cell (cb[n] = cells).
+struct BinGeom {
+    uint32_t n_chrom, shift;
+    uint32_t off[BITS_MAX_CHROM + 1];
+    uint32_t cb[BITS_MAX_CHROM + 1];
+};
+
+// The first key of region r, and #{B_S < key_lo}, #{B_E < key_lo}.
+struct RegionDesc {
+    uint32_t key_lo, s_lo, e_lo, pad;
+};
+
+__device__ __forceinline__ uint32_t chrom_of_cell(const BinGeom& g, uint32_t c) {
+    uint32_t lo = 0, hi = g.n_chrom;   // last k with cb[k] <= c (chromosomes without cells are skipped)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (g.cb[mid] <= c) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// #{K[0..m) < x} (STRICT) or #{K[0..m) <= x}; the same number of steps for
+// every lane at a given m.
+template <bool STRICT>
+__device__ __forceinline__ uint32_t rank_in(const uint32_t* K, uint32_t m, uint32_t x) {
+    if (m == 0) return 0;
+    uint32_t base = 0, len = m;
+    while (len > 1) {
+        const uint32_t half = len >> 1;
+        const uint32_t k = K[base + half];
+        if (STRICT ? (k < x) : (k <= x)) base += half;
+        len -= half;
+    }
+    const uint32_t k = K[base];
+    return base + (STRICT ? (k < x) : (k <= x));
+}
+
+// #{bs <= x} over the whole array, given that bs[j - 1] <= x (j >= 1) or j = 0.
+__device__ uint32_t gallop_le(const uint32_t* __restrict__ bs, uint32_t n, uint32_t j, uint32_t x) {
+    uint32_t lo = j, hi = n;
+    uint64_t step = 1;
+    while (true) {
+        const uint64_t probe = (uint64_t)lo + step - 1;
+        if (probe >= n) break;
+        if (bs[probe] <= x) {
+            lo = (uint32_t)probe + 1u;
+            step <<= 1;
+        } else {
+            hi = (uint32_t)probe;
+            break;
+        }
+    }
+    return lo + rank_in<false>(bs + lo, hi - lo, x);
+}
+
+// Exclusive scan of h[0..m) in place (m <= per * blockDim with per <= 8);
+// returns the total.  wsum holds blockDim / 64 words.
+__device__ uint32_t block_scan_u32(uint32_t* h, uint32_t m, uint32_t* wsum) {
+    const uint32_t per = (m + blockDim.x - 1) / blockDim.x;
+    const uint32_t b0 = threadIdx.x * per;
+    uint32_t mine = 0;
+    for (uint32_t k = 0; k < per; ++k)
+        if (b0 + k < m) mine += h[b0 + k];
+    const uint32_t lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint32_t x = mine;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    if (lane == kWave - 1) wsum[w] = x;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (uint32_t k = 0; k < blockDim.x / kWave; ++k) {
+        if (k < w) pre += wsum[k];
+        tot += wsum[k];
+    }
+    pre += x - mine;
+    for (uint32_t k = 0; k < per; ++k) {
+        if (b0 + k < m) {
+            const uint32_t v = h[b0 + k];
+            h[b0 + k] = pre;
+            pre += v;
+        }
+    }
+    __syncthreads();
+    return tot;
+}
+
+// Ranks of every cell's first coordinate in B_S and B_E.
+__global__ void __launch_bounds__(256) k_bin_cells(BinGeom g, const uint32_t* __restrict__ bs,
+                                                   const uint32_t* __restrict__ be, uint32_t n,
+                                                   uint32_t* __restrict__ rs, uint32_t* __restrict__ re) {
+    const uint32_t ncells = g.cb[g.n_chrom];
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncells; c += gridDim.x * blockDim.x) {
+        const uint32_t k = chrom_of_cell(g, c);
+        const uint32_t lo = g.off[k] + ((c - g.cb[k]) << g.shift);
+        rs[c] = rank_in<true>(bs, n, lo);
+        re[c] = rank_in<true>(be, n, lo);
+    }
+}
+
+// flag[c] = 1 where a region starts: the first cell of a chromosome, or the
+// merged count since the chromosome's start enters a new multiple of kRegionKeys.
+__global__ void __launch_bounds__(256) k_bin_flags(BinGeom g, const uint32_t* __restrict__ rs,
+                                                   const uint32_t* __restrict__ re, uint32_t* __restrict__ flag) {
+    const uint32_t ncells = g.cb[g.n_chrom];
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncells; c += gridDim.x * blockDim.x) {
+        const uint32_t k = chrom_of_cell(g, c), c0 = g.cb[k];
+        uint32_t f = 1u;
+        if (c != c0) {
+            const uint64_t base = (uint64_t)rs[c0] + re[c0];
+            const uint64_t p = (uint64_t)rs[c] + re[c] - base, q = (uint64_t)rs[c - 1] + re[c - 1] - base;
+            f = (p / kRegionKeys) != (q / kRegionKeys) ? 1u : 0u;
+        }
+        flag[c] = f;
+    }
+}
+
+// cell -> region (offsets = exclusive scan of the flags), region descriptors,
+// and the sentinel after the last region: {genome size, n, n}.
+__global__ void __launch_bounds__(256) k_bin_regions(BinGeom g, const uint32_t* __restrict__ rs,
+                                                     const uint32_t* __restrict__ re,
+                                                     const uint32_t* __restrict__ flag,
+                                                     const uint64_t* __restrict__ offsets, uint32_t n,
+                                                     uint32_t nreg_max, uint32_t* __restrict__ cell_region,
+                                                     RegionDesc* __restrict__ desc, uint32_t* status) {
+    const uint32_t ncells = g.cb[g.n_chrom];
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncells; c += gridDim.x * blockDim.x) {
+        uint32_t rid = (uint32_t)(offsets[c + 1] - 1u);
+        if (rid >= nreg_max) {          // cannot happen (nreg_max bounds the count); never index past it
+            atomicOr(status, BITS_FLAG_CHROM);
+            rid = nreg_max - 1u;
+        }
+        cell_region[c] = rid;
+        if (flag[c]) {
+            const uint32_t k = chrom_of_cell(g, c);
+            desc[rid] = RegionDesc{g.off[k] + ((c - g.cb[k]) << g.shift), rs[c], re[c], 0u};
+        }
+        if (c == ncells - 1) desc[rid + 1] = RegionDesc{g.off[g.n_chrom], n, n, 0u};   // desc has nreg_max + 1
+    }
+}
+
+// Binning of shuffles [sb, sb + nb): workgroup (k, s) makes the placements of
+// chromosome k's queries (table positions [cursor[k] - hist[k], cursor[k]))
+// in shuffle sb + s, counts them per region, writes the segment table of
+// (s, every region of k), and writes the records {start, end} in region
+// order to recs[s * na + table position range].
+__global__ void __launch_bounds__(kBinThreads) k_bin_place(
+    BinGeom g, const uint32_t* __restrict__ off, const uint32_t* __restrict__ span, const uint32_t* __restrict__ len,
+    const uint32_t* __restrict__ idx, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ cursor,
+    uint64_t na, uint64_t seed, uint64_t sb, uint32_t nb, const uint32_t* __restrict__ cell_region,
+    const uint64_t* __restrict__ offsets, uint32_t nreg_max, uint32_t* __restrict__ seg_start,
+    uint32_t* __restrict__ seg_cnt, uint2* __restrict__ recs) {
+    __shared__ uint16_t cr[kMaxCells];
+    __shared__ uint32_t h[kMaxCells];
+    __shared__ uint32_t wsum[kBinThreads / kWave];
+    const uint32_t k = blockIdx.x / nb, s = blockIdx.x - k * nb;
+    const uint32_t c0 = g.cb[k], nc = g.cb[k + 1] - c0;
+    if (nc == 0) return;   // no cells: no regions, no queries (an empty chromosome holds none)
+    const uint32_t nreg = (uint32_t)offsets[g.cb[g.n_chrom]];
+    const uint32_t rb = cell_region[c0];
+    const uint32_t rl = (k + 1 < g.n_chrom && g.cb[k + 1] < g.cb[g.n_chrom]) ? cell_region[g.cb[k + 1]] : nreg;
+    // regions of chromosome k (<= nc <= kMaxCells; the clamps only matter for an inconsistent
+    // table, which k_bin_regions has already flagged)
+    const uint32_t nr = rl > rb ? min(min(rl - rb, nc), nreg_max - rb) : 0u;
+    for (uint32_t j = threadIdx.x; j < nc; j += blockDim.x) cr[j] = (uint16_t)(cell_region[c0 + j] - rb);
+    for (uint32_t j = threadIdx.x; j < nr; j += blockDim.x) h[j] = 0u;
+    __syncthreads();
+    const uint32_t g1 = cursor[k], g0 = g1 - hist[k];
+    const uint32_t ok = g.off[k], sh = g.shift;
+    const uint64_t gs = (sb + s) * na;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (uint32_t p = g0 + threadIdx.x; p < g1; p += blockDim.x) {
+        const uint32_t sp = span[p];
+        if (!sp) continue;
+        const uint32_t st = mc_place(gs + idx[p], k0, k1, off[p], sp);
+        const uint32_t lr = cr[(st - ok) >> sh];
+        if (lr < nr) atomicAdd(&h[lr], 1u);
+    }
+    __syncthreads();
+    uint32_t* ss = seg_start + (uint64_t)s * nreg_max + rb;
+    uint32_t* sc = seg_cnt + (uint64_t)s * nreg_max + rb;
+    for (uint32_t j = threadIdx.x; j < nr; j += blockDim.x) sc[j] = h[j];
+    __syncthreads();
+    block_scan_u32(h, nr, wsum);
+    for (uint32_t j = threadIdx.x; j < nr; j += blockDim.x) ss[j] = g0 + h[j];
+    __syncthreads();
+    uint2* out = recs + (uint64_t)s * na;
+    for (uint32_t p = g0 + threadIdx.x; p < g1; p += blockDim.x) {
+        const uint32_t sp = span[p];
+        if (!sp) continue;
+        const uint32_t st = mc_place(gs + idx[p], k0, k1, off[p], sp);
+        const uint32_t lr = cr[(st - ok) >> sh];
+        if (lr >= nr) continue;
+        const uint32_t at = atomicAdd(&h[lr], 1u);
+        out[g0 + at] = make_uint2(st, st + (len[p] - 1u));
+    }
+}
+
+// The placements of one region, counted against slices S = B_S[s_lo, s_lo + ns)
+// and E = B_E[e_lo, e_lo + ne) (in LDS, or in HBM for an oversize region).
+template <bool LDS>
+__device__ __forceinline__ void bin_count_region(const uint32_t* S, uint32_t ns, const uint32_t* E, uint32_t ne,
+                                                 const uint32_t* __restrict__ bs, uint32_t n, uint32_t s_lo,
+                                                 uint32_t e_lo, const uint2* __restrict__ recs, uint64_t na,
+                                                 const uint64_t* pre, const uint32_t* sst, uint32_t nb,
+                                                 unsigned long long* acc) {
+    const uint64_t total = pre[nb];
+    const uint32_t s_end = s_lo + ns;
+    for (uint64_t p = threadIdx.x; p < total; p += blockDim.x) {
+        // shuffle of p: the last s with pre[s] <= p (segment s is then non-empty)
+        uint32_t lo = 0, hi = nb;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (pre[mid] <= p) lo = mid; else hi = mid;
+        }
+        const uint2 r = recs[(uint64_t)lo * na + sst[lo] + (p - pre[lo])];
+        uint32_t first;
+        if (r.y == 0xFFFFFFFFu) {
+            first = n;
+        } else {
+            const uint32_t c = rank_in<false>(S, ns, r.y);
+            first = (c == ns && s_end < n) ? gallop_le(bs, n, s_end, r.y) : s_lo + c;
+        }
+        const uint32_t last = e_lo + rank_in<true>(E, ne, r.x);
+        atomicAdd(&acc[lo], (unsigned long long)(first - last));
+    }
+}
+
+// One workgroup per region r < nreg (nreg on the device; workgroups past it
+// return): stage the slices, count every placement of the batch that starts
+// in the region, write partial[r * nb + s].
+__global__ void __launch_bounds__(kBinThreads) k_bin_search(
+    const uint32_t* __restrict__ bs, const uint32_t* __restrict__ be, uint32_t n,
+    const RegionDesc* __restrict__ desc, const uint64_t* __restrict__ nreg_p, const uint32_t* __restrict__ seg_start,
+    const uint32_t* __restrict__ seg_cnt, uint32_t nreg_max, uint32_t nb, const uint2* __restrict__ recs,
+    uint64_t na, unsigned long long* __restrict__ partial) {
+    __shared__ uint32_t slice[kSliceWords];
+    __shared__ uint64_t pre[BITS_MC_BIN_MAX_BATCH + 1];
+    __shared__ uint32_t sst[BITS_MC_BIN_MAX_BATCH];
+    __shared__ unsigned long long acc[BITS_MC_BIN_MAX_BATCH];
+    __shared__ uint64_t w64[kBinThreads / kWave];
+    const uint32_t r = blockIdx.x;
+    if (r >= *nreg_p) return;
+    const RegionDesc d0 = desc[r], d1 = desc[r + 1];
+    const uint32_t s_lo = d0.s_lo, e_lo = d0.e_lo;
+    const uint32_t s_end = (uint32_t)min((uint64_t)d1.s_lo + kMargin, (uint64_t)n);
+    const uint32_t ns = s_end - s_lo, ne = d1.e_lo - e_lo;
+    // per-shuffle segment starts and the prefix of their lengths (uint64: nb * na may pass 2^32)
+    uint32_t cnt = 0;
+    if (threadIdx.x < nb) {
+        sst[threadIdx.x] = seg_start[(uint64_t)threadIdx.x * nreg_max + r];
+        cnt = seg_cnt[(uint64_t)threadIdx.x * nreg_max + r];
+        acc[threadIdx.x] = 0ull;
+    }
+    {
+        const uint32_t lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+        uint64_t x = cnt;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint64_t y = __shfl_up(x, o);
+            if (lane >= (uint32_t)o) x += y;
+        }
+        if (lane == kWave - 1) w64[w] = x;
+        __syncthreads();
+        uint64_t before = 0;
+        for (uint32_t j = 0; j < w; ++j) before += w64[j];
+        if (threadIdx.x < nb) pre[threadIdx.x] = before + x - cnt;
+        if (threadIdx.x == nb - 1) pre[nb] = before + x;
+    }
+    const bool in_lds = (uint64_t)ns + ne <= kSliceWords;
+    if (in_lds) {
+        for (uint32_t j = threadIdx.x; j < ns; j += blockDim.x) slice[j] = bs[s_lo + j];
+        for (uint32_t j = threadIdx.x; j < ne; j += blockDim.x) slice[ns + j] = be[e_lo + j];
+    }
+    __syncthreads();
+    if (in_lds)
+        bin_count_region<true>(slice, ns, slice + ns, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb, acc);
+    else
+        bin_count_region<false>(bs + s_lo, ns, be + e_lo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb, acc);
+    __syncthreads();
+    if (threadIdx.x < nb) partial[(uint64_t)r * nb + threadIdx.x] = acc[threadIdx.x];
+}
+
+// totals[s] += sum over regions r < nreg of partial[r * nb + s]; blockIdx.y
+// takes every gridDim.y-th region.
+__global__ void __launch_bounds__(256) k_bin_reduce(const unsigned long long* __restrict__ partial,
+                                                    const uint64_t* __restrict__ nreg_p, uint32_t nb,
+                                                    unsigned long long* __restrict__ totals) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nb) return;
+    const uint64_t nreg = *nreg_p;
+    unsigned long long v = 0ull;
+    for (uint64_t r = blockIdx.y; r < nreg; r += gridDim.y) v += partial[r * nb + s];
+    if (v) atomicAdd(totals + s, v);
+}
+
+// Cell shift and per-chromosome cell bases of a genome; false if no shift
+// keeps every chromosome within kMaxCells cells (impossible below 2^32 bp).
+bool bin_geometry(const uint32_t* chrom_len, uint32_t n_chrom, BinGeom* g) {
+    uint64_t maxlen = 0, acc = 0;
+    for (uint32_t k = 0; k < n_chrom; ++k) maxlen = chrom_len[k] > maxlen ? chrom_len[k] : maxlen;
+    uint32_t sh = kMinShift;
+    while (sh < 32 && ((maxlen + (1ull << sh) - 1) >> sh) > kMaxCells) ++sh;
+    if (sh >= 32) return false;
+    g->n_chrom = n_chrom;
+    g->shift = sh;
+    uint64_t cells = 0;
+    for (uint32_t k = 0; k < n_chrom; ++k) {
+        g->off[k] = (uint32_t)acc;
+        g->cb[k] = (uint32_t)cells;
+        acc += chrom_len[k];
+        cells += ((uint64_t)chrom_len[k] + (1ull << sh) - 1) >> sh;
+    }
+    if (acc > 0xFFFFFFFFull || cells > 0xFFFFFFFFull) return false;
+    for (uint32_t k = n_chrom; k <= BITS_MAX_CHROM; ++k) {
+        g->off[k] = (uint32_t)acc;
+        g->cb[k] = (uint32_t)cells;
+    }
+    return true;
+}
+
+}  // namespace
+
+bool bin_layout(const uint32_t* chrom_len, uint32_t n_chrom, uint64_t n, BinLayout* L) {
+    BinGeom g;
+    if (!bin_geometry(chrom_len, n_chrom, &g)) return false;
+    L->ncells = g.cb[n_chrom];
+    uint64_t with_cells = 0;
+    for (uint32_t k = 0; k < n_chrom; ++k) with_cells += g.cb[k + 1] > g.cb[k];
+    const uint64_t bound = with_cells + (2 * n) / kRegionKeys;
+    L->nreg_max = L->ncells < bound ? L->ncells : bound;
+    return true;
+}
+
+hipError_t launch_bin_regions(const uint32_t* chrom_len, uint32_t n_chrom, const uint32_t* bs, const uint32_t* be,
+                              uint32_t n, const BinWs& w, uint32_t* status, hipStream_t s) {
+    BinGeom g;
+    if (!bin_geometry(chrom_len, n_chrom, &g)) return hipErrorInvalidValue;
+    const uint32_t ncells = g.cb[n_chrom];
+    if (!ncells) return hipErrorInvalidValue;
+    const uint32_t gr = (uint32_t)std::min<uint64_t>((ncells + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_bin_cells, dim3(gr), dim3(256), 0, s, g, bs, be, n, w.rs, w.re);
+    hipLaunchKernelGGL(k_bin_flags, dim3(gr), dim3(256), 0, s, g, w.rs, w.re, w.flag);
+    hipError_t e = launch_scan_counts(w.flag, ncells, w.offsets, w.scan_tiles, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bin_regions, dim3(gr), dim3(256), 0, s, g, w.rs, w.re, w.flag, w.offsets, n, w.nreg_max,
+                       w.cell_region, reinterpret_cast<RegionDesc*>(w.desc), status);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_batch(const uint32_t* chrom_len, uint32_t n_chrom, const McTable& tab, uint64_t na,
+                            const uint32_t* bs, const uint32_t* be, uint32_t n, uint64_t seed, uint64_t sb,
+                            uint32_t nb, const BinWs& w, unsigned long long* totals, hipStream_t s) {
+    BinGeom g;
+    if (!bin_geometry(chrom_len, n_chrom, &g)) return hipErrorInvalidValue;
+    if (nb == 0 || nb > BITS_MC_BIN_MAX_BATCH) return hipErrorInvalidValue;
+    const uint32_t ncells = g.cb[n_chrom];
+    hipLaunchKernelGGL(k_bin_place, dim3(n_chrom * nb), dim3(kBinThreads), 0, s, g, tab.off, tab.span, tab.len,
+                       tab.idx, tab.hist, tab.cursor, na, seed, sb, nb, w.cell_region, w.offsets, w.nreg_max,
+                       w.seg_start, w.seg_cnt, reinterpret_cast<uint2*>(w.recs));
+    hipLaunchKernelGGL(k_bin_search, dim3(w.nreg_max), dim3(kBinThreads), 0, s, bs, be, n,
+                       reinterpret_cast<const RegionDesc*>(w.desc), w.offsets + ncells, w.seg_start, w.seg_cnt,
+                       w.nreg_max, nb, reinterpret_cast<const uint2*>(w.recs), na, w.partial);
+    const uint32_t gy = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(w.nreg_max / 64, 1), 256);
+    hipLaunchKernelGGL(k_bin_reduce, dim3((nb + 255) / 256, gy), dim3(256), 0, s, w.partial, w.offsets + ncells, nb,
+                       totals);
+    return hipGetLastError();
+}
+
+}  // namespace bits

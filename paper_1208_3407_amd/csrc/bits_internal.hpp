@@ -65,6 +65,17 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
     }
 }
 
+// Start of a query's placement in shuffle s (Sec. 3.2): counter g = s * na + i
+// (i the query's input index), key = the seed; the 64-bit draw u = (c1, c0)
+// scaled to [0, span) by a high multiply, span > 0 being the number of legal
+// starts of the query in its chromosome, which begins at `off`.
+__device__ __forceinline__ uint32_t mc_place(uint64_t g, uint32_t k0, uint32_t k1, uint32_t off, uint32_t span) {
+    uint32_t c0 = (uint32_t)g, c1 = (uint32_t)(g >> 32), c2 = 0u, c3 = 0u;
+    philox4x32_10(c0, c1, c2, c3, k0, k1);
+    const uint64_t u = ((uint64_t)c1 << 32) | c0;
+    return off + (uint32_t)__umul64hi(u, (uint64_t)span);
+}
+
 // ------------------------------------------------------------------ search arguments
 
 struct SearchArgs {
@@ -195,6 +206,30 @@ hipError_t launch_place_rounds(const McTable& tab, const uint32_t* b_start, uint
 hipError_t launch_count_rounds(const uint32_t* S, const uint32_t* E, uint64_t nb, uint32_t rounds, const uint32_t* as,
                                const uint32_t* ae, uint64_t na, unsigned long long* totals, uint32_t* status,
                                hipStream_t s);
+// binned.hip: the Monte-Carlo path binned by genome region.
+struct BinLayout {
+    uint64_t ncells, nreg_max;
+};
+// Cell count and an upper bound on the region count for a genome and |B| = n;
+// false if the genome cannot be cut (sizes past 2^32).
+bool bin_layout(const uint32_t* chrom_len, uint32_t n_chrom, uint64_t n, BinLayout* L);
+struct BinWs {                    // device buffers, carved from the caller's workspace
+    uint32_t *rs, *re, *flag;     // [ncells]
+    uint64_t* offsets;            // [ncells + 1]: region starts (exclusive scan of flag); offsets[ncells] = regions
+    uint64_t* scan_tiles;         // scan_tiles(ncells)
+    uint32_t* cell_region;        // [ncells]
+    void* desc;                   // [nreg_max + 1] region descriptors (16 bytes)
+    uint32_t *seg_start, *seg_cnt;    // [batch][nreg_max]
+    unsigned long long* partial;      // [nreg_max][batch]
+    void* recs;                       // [batch][na] {start, end}
+    uint32_t nreg_max;
+};
+hipError_t launch_bin_regions(const uint32_t* chrom_len, uint32_t n_chrom, const uint32_t* bs, const uint32_t* be,
+                              uint32_t n, const BinWs& w, uint32_t* status, hipStream_t s);
+// Shuffles [sb, sb + nb) (absolute indices); totals points at shuffle sb's slot.
+hipError_t launch_bin_batch(const uint32_t* chrom_len, uint32_t n_chrom, const McTable& tab, uint64_t na,
+                            const uint32_t* bs, const uint32_t* be, uint32_t n, uint64_t seed, uint64_t sb,
+                            uint32_t nb, const BinWs& w, unsigned long long* totals, hipStream_t s);
 hipError_t launch_mc_tail(const unsigned long long* totals, uint64_t nshuf, const unsigned long long* observed,
                           unsigned long long* n_ge, unsigned long long* n_le, hipStream_t s);
 hipError_t launch_project(const uint32_t* chrom_len, uint32_t n_chrom, const uint32_t* chrom,

@@ -834,14 +834,6 @@ __host__ __device__ constexpr size_t sort_lds_bytes(uint32_t block) {
 }
 static_assert((kMaxChunk << kSortQBits) <= 65536, "sort meta");
 
-// Start of the placement of a query with legal-start count span > 0.
-__device__ __forceinline__ uint32_t mc_place(uint64_t g, uint32_t k0, uint32_t k1, uint32_t off, uint32_t span) {
-    uint32_t c0 = (uint32_t)g, c1 = (uint32_t)(g >> 32), c2 = 0u, c3 = 0u;
-    philox4x32_10(c0, c1, c2, c3, k0, k1);
-    const uint64_t u = ((uint64_t)c1 << 32) | c0;
-    return off + (uint32_t)__umul64hi(u, (uint64_t)span);
-}
-
 // In-place exclusive scan of kSortBuckets counters by the whole workgroup;
 // returns the total.
 __device__ __forceinline__ uint32_t block_scan_buckets(uint32_t* h, uint32_t* wsum) {

@@ -1,0 +1,148 @@
+"""GPU parity of the region-binned Monte-Carlo path (Sec. 3.2) through the C
+ABI: per-shuffle totals, observed total and tails against the oracle and,
+bit for bit, against the query-ordered path (bits_mc_pvalue), over uneven
+batches of shuffles, region layouts that exercise the LDS slices, the
+margin past a region's end, ends that continue in HBM, oversize regions
+(duplicated keys) searched in HBM, empty chromosomes, and bad queries."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+from paper_1208_3407_amd import bits, datagen  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+
+
+def up(x):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.uint32))).to(DEV)
+
+
+def down(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def check(lengths, a_s, a_e, b_s, b_e, seed, s0, s1, batch, learned=False, against_pvalue=True):
+    """bits_mc_binned against the oracle (and against bits_mc_pvalue on the same reference)."""
+    exp = oracle.mc_totals(np.sort(b_s), np.sort(b_e), oracle.mc_prepare(lengths, a_s, a_e), seed, s0, s1,
+                           threads=8)
+    obs = oracle.counter(a_s, a_e, b_s, b_e)[1]
+    ref = bits.bits_sort_ref(up(b_s), up(b_e), learned=learned, train={"epochs": 10})
+    mc = bits.bits_mc_binned(ref, up(a_s), up(a_e), lengths, seed, s0, s1, batch=batch)
+    got = down(mc.totals)
+    assert np.array_equal(got, exp), np.flatnonzero(got != exp)[:10]
+    assert int(down(mc.observed)[0]) == obs
+    assert (int(down(mc.n_ge)[0]), int(down(mc.n_le)[0])) == oracle.mc_tail(exp, obs)
+    assert bits.bits_get_status(ref) == 0
+    if against_pvalue:
+        pv = bits.bits_mc_pvalue(ref, up(a_s), up(a_e), lengths, seed, s0, s1)
+        assert np.array_equal(down(pv.totals), got)
+    return got
+
+
+@pytest.mark.parametrize("batch", [1, 3, 64, 1024])
+def test_binned_matches_oracle_w2(batch):
+    """Multi-chromosome genome, clustered B (the Monte-Carlo recipe), uneven batches, s0 > 0."""
+    note("case: binned w2 batch=%d" % batch)
+    lengths, A, B = datagen.w2_sets(seed=2, n_a=3000, n_b=60_000)
+    a_s, a_e = oracle.project(lengths, A.chrom, A.start, A.end)
+    b_s, b_e = oracle.project(lengths, B.chrom, B.start, B.end)
+    check(lengths, a_s, a_e, b_s, b_e, 7, 5, 22, batch, learned=batch == 64)
+
+
+def test_binned_many_regions_and_long_queries():
+    """One chromosome, dense B (many regions of ~8192 keys), queries up to 100 kbp
+    long so that ends cross the staged margin and continue in HBM."""
+    note("case: binned dense, long queries")
+    r = np.random.default_rng(11)
+    L = np.array([4_000_000], np.uint32)
+    nb = 400_000
+    b_s = r.integers(0, 3_990_000, nb).astype(np.uint32)
+    b_e = b_s + r.integers(0, 2000, nb).astype(np.uint32)
+    na = 2000
+    a_s = r.integers(0, 3_800_000, na).astype(np.uint32)
+    a_e = a_s + r.integers(0, 100_000, na).astype(np.uint32)
+    check(L, a_s, a_e, b_s, b_e, 3, 0, 9, 4)
+
+
+def test_binned_oversize_region_and_empty_chromosomes():
+    """Empty chromosomes between non-empty ones, 12,000 intervals of B on one
+    coordinate (a region too large for LDS, searched in HBM), B keys past the
+    genome's end, and a 1-bp chromosome."""
+    note("case: binned oversize, empty chromosomes")
+    r = np.random.default_rng(12)
+    L = np.array([0, 500_000, 0, 0, 300_000, 1], np.uint32)
+    b_s = np.concatenate([np.full(12_000, 1234, np.uint32), r.integers(0, 800_001, 20_000).astype(np.uint32),
+                          np.full(10, 900_000, np.uint32)])
+    b_e = b_s + r.integers(0, 50, len(b_s)).astype(np.uint32)
+    a_s = np.concatenate([r.integers(0, 499_000, 300), r.integers(500_000, 799_000, 300), [800_000]]).astype(np.uint32)
+    cap = np.where(a_s < 500_000, 499_999, np.where(a_s < 800_000, 799_999, 800_000))
+    a_e = np.minimum(a_s + r.integers(0, 1000, len(a_s)), cap).astype(np.uint32)
+    check(L, a_s, a_e, b_s, b_e, 9, 2, 12, 5)
+
+
+def test_binned_w0_single_chromosome():
+    """The small single-chromosome workload (10 Mbp, 1e4 x 1e4)."""
+    note("case: binned w0")
+    lengths, A, B = datagen.w0_sets(seed=1)
+    a_s, a_e = oracle.project(lengths, A.chrom, A.start, A.end)
+    b_s, b_e = oracle.project(lengths, B.chrom, B.start, B.end)
+    check(lengths, a_s, a_e, b_s, b_e, 7, 0, 33, 16)
+
+
+def test_binned_edges():
+    """Empty shuffle range, empty query set, empty reference, a query outside its
+    chromosome (flagged, left out), batch outside [1, 1024]."""
+    note("case: binned edges")
+    lengths, A, B = datagen.w2_sets(seed=3, n_a=500, n_b=5000)
+    a_s, a_e = oracle.project(lengths, A.chrom, A.start, A.end)
+    b_s, b_e = oracle.project(lengths, B.chrom, B.start, B.end)
+    ref = bits.bits_sort_ref(up(b_s), up(b_e))
+    mc = bits.bits_mc_binned(ref, up(a_s), up(a_e), lengths, 7, 4, 4)
+    assert len(mc.totals) == 0 and int(down(mc.observed)[0]) == oracle.counter(a_s, a_e, b_s, b_e)[1]
+    assert (int(down(mc.n_ge)[0]), int(down(mc.n_le)[0])) == (0, 0)
+    mc = bits.bits_mc_binned(ref, up(np.zeros(0)), up(np.zeros(0)), lengths, 7, 0, 5)
+    assert down(mc.totals).tolist() == [0] * 5 and int(down(mc.observed)[0]) == 0
+    empty = bits.bits_sort_ref(up(np.zeros(0)), up(np.zeros(0)))
+    mc = bits.bits_mc_binned(empty, up(a_s), up(a_e), lengths, 7, 0, 5)
+    assert down(mc.totals).tolist() == [0] * 5
+    # the last query crosses the end of its chromosome: flagged and left out
+    bad_s, bad_e = a_s.copy(), a_e.copy()
+    off = np.concatenate([[0], np.cumsum(lengths.astype(np.uint64))])
+    c = int(np.searchsorted(off, bad_s[-1], side="right") - 1)
+    bad_e[-1] = np.uint32(off[c + 1] + 5)
+    mc = bits.bits_mc_binned(ref, up(bad_s), up(bad_e), lengths, 7, 0, 6, batch=4)
+    assert bits.bits_get_status(ref) & bits.BITS_FLAG_CHROM
+    bits.bits_clear_status(ref)
+    # the other queries keep their own counters g = s * na + i: the same totals as the
+    # query-ordered path, which leaves the bad query out the same way
+    pv = bits.bits_mc_pvalue(ref, up(bad_s), up(bad_e), lengths, 7, 0, 6)
+    assert np.array_equal(down(mc.totals), down(pv.totals))
+    assert int(down(mc.observed)[0]) == int(down(pv.observed)[0])
+    bits.bits_clear_status(ref)
+    for b in (0, 1025):
+        with pytest.raises(bits.BitsError):
+            bits.bits_mc_binned(ref, up(a_s), up(a_e), lengths, 7, 0, 5, batch=b)
+
+
+def test_binned_at_monte_carlo_scale():
+    """1e5 queries x 40 shuffles against 2e6 clustered intervals on the 24-chromosome
+    genome: equal to the learned query-ordered path bit for bit, and to the oracle."""
+    note("case: binned scale")
+    lengths, A, B = datagen.w2_sets(seed=4, n_a=100_000, n_b=2_000_000)
+    a_s, a_e = oracle.project(lengths, A.chrom, A.start, A.end)
+    b_s, b_e = oracle.project(lengths, B.chrom, B.start, B.end)
+    check(lengths, a_s, a_e, b_s, b_e, 7, 0, 40, 16, learned=True)
