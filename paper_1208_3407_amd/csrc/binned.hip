@@ -58,19 +58,25 @@ __device__ __forceinline__ uint32_t chrom_of_cell(const BinGeom& g, uint32_t c) 
     return lo;
 }
 
-// #{K[0..m) < x} (STRICT) or #{K[0..m) <= x}; the same number of steps for
-// every lane at a given m.
-template <bool STRICT>
+// Word of element j of a slice staged in LDS with one spare word after every
+// 32: the bisection's probes sit at power-of-two distances, which without
+// the skew would fall into a few of the 32 LDS banks.
+__host__ __device__ constexpr uint32_t skew(uint32_t j) { return j + (j >> 5); }
+__host__ __device__ constexpr uint64_t skewed_len(uint64_t m) { return m + (m >> 5) + 1; }
+
+// #{K[0..m) < x} (STRICT) or #{K[0..m) <= x} (K skewed when SKEW); the same
+// number of steps for every lane at a given m.
+template <bool STRICT, bool SKEW = false>
 __device__ __forceinline__ uint32_t rank_in(const uint32_t* K, uint32_t m, uint32_t x) {
     if (m == 0) return 0;
     uint32_t base = 0, len = m;
     while (len > 1) {
         const uint32_t half = len >> 1;
-        const uint32_t k = K[base + half];
+        const uint32_t k = K[SKEW ? skew(base + half) : base + half];
         if (STRICT ? (k < x) : (k <= x)) base += half;
         len -= half;
     }
-    const uint32_t k = K[base];
+    const uint32_t k = K[SKEW ? skew(base) : base];
     return base + (STRICT ? (k < x) : (k <= x));
 }
 
@@ -237,33 +243,70 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_place(
     }
 }
 
+// Wave-level segmented sum: lanes carry (key, value) with the keys of the
+// valid lanes non-decreasing in lane order; each run of equal keys adds its
+// sum to acc[key] with at most two LDS atomics (the run's inclusive prefix at
+// its last lane, minus the prefix before its first lane).  T = uint32_t only
+// when 64 values cannot reach 2^32.
+template <typename T>
+__device__ __forceinline__ void wave_segment_add(uint32_t key, T v, bool valid, unsigned long long* acc) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    T x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const T y = __shfl_up(x, o);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    const uint32_t kp = __shfl_up(key, 1), kn = __shfl_down(key, 1);
+    const T xp = __shfl_up(x, 1);
+    if (!valid) return;
+    if (lane == kWave - 1 || kn != key) atomicAdd(&acc[key], (unsigned long long)x);
+    if (lane != 0 && kp != key) atomicAdd(&acc[key], 0ull - (unsigned long long)xp);
+}
+
 // The placements of one region, counted against slices S = B_S[s_lo, s_lo + ns)
-// and E = B_E[e_lo, e_lo + ne) (in LDS, or in HBM for an oversize region).
-template <bool LDS>
+// and E = B_E[e_lo, e_lo + ne) (skewed in LDS, or plain in HBM for an
+// oversize region).  Each wave takes a contiguous range of the region's
+// records, 64 per step; records are grouped by shuffle (pre[s] = first
+// record of shuffle s), so a wave tracks its shuffle by a forward scan and
+// adds per-shuffle sums with wave_segment_add.
+template <bool LDS, typename T>
 __device__ __forceinline__ void bin_count_region(const uint32_t* S, uint32_t ns, const uint32_t* E, uint32_t ne,
                                                  const uint32_t* __restrict__ bs, uint32_t n, uint32_t s_lo,
                                                  uint32_t e_lo, const uint2* __restrict__ recs, uint64_t na,
                                                  const uint64_t* pre, const uint32_t* sst, uint32_t nb,
                                                  unsigned long long* acc) {
+    const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const uint64_t total = pre[nb];
+    const uint64_t steps = (total + kWave - 1) / kWave, per = (steps + nw - 1) / nw;
+    const uint64_t p0 = (uint64_t)wv * per * kWave, p1 = min(total, p0 + per * kWave);
+    if (p0 >= p1) return;
     const uint32_t s_end = s_lo + ns;
-    for (uint64_t p = threadIdx.x; p < total; p += blockDim.x) {
-        // shuffle of p: the last s with pre[s] <= p (segment s is then non-empty)
-        uint32_t lo = 0, hi = nb;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (pre[mid] <= p) lo = mid; else hi = mid;
+    // shuffle of the wave's first record: the last s with pre[s] <= p0
+    uint32_t sw = 0, hi = nb;
+    while (hi - sw > 1) {
+        const uint32_t mid = (sw + hi) >> 1;
+        if (pre[mid] <= p0) sw = mid; else hi = mid;
+    }
+    for (uint64_t b = p0; b < p1; b += kWave) {
+        const uint64_t p = b + lane;
+        const bool valid = p < p1;
+        uint32_t sl = sw;
+        T v = 0;
+        if (valid) {
+            while (pre[sl + 1] <= p) ++sl;   // ends at sl < nb: p < pre[nb]
+            const uint2 r = recs[(uint64_t)sl * na + sst[sl] + (p - pre[sl])];
+            uint32_t first;
+            if (r.y == 0xFFFFFFFFu) {
+                first = n;
+            } else {
+                const uint32_t c = rank_in<false, LDS>(S, ns, r.y);
+                first = (c == ns && s_end < n) ? gallop_le(bs, n, s_end, r.y) : s_lo + c;
+            }
+            v = (T)(first - (e_lo + rank_in<true, LDS>(E, ne, r.x)));
         }
-        const uint2 r = recs[(uint64_t)lo * na + sst[lo] + (p - pre[lo])];
-        uint32_t first;
-        if (r.y == 0xFFFFFFFFu) {
-            first = n;
-        } else {
-            const uint32_t c = rank_in<false>(S, ns, r.y);
-            first = (c == ns && s_end < n) ? gallop_le(bs, n, s_end, r.y) : s_lo + c;
-        }
-        const uint32_t last = e_lo + rank_in<true>(E, ne, r.x);
-        atomicAdd(&acc[lo], (unsigned long long)(first - last));
+        wave_segment_add<T>(valid ? sl : 0xFFFFFFFFu, v, valid, acc);
+        sw = __shfl(sl, kWave - 1);
     }
 }
 
@@ -308,16 +351,25 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_search(
         if (threadIdx.x < nb) pre[threadIdx.x] = before + x - cnt;
         if (threadIdx.x == nb - 1) pre[nb] = before + x;
     }
-    const bool in_lds = (uint64_t)ns + ne <= kSliceWords;
+    const uint32_t eo = (uint32_t)skewed_len(ns);   // E's first word
+    const bool in_lds = skewed_len(ns) + skewed_len(ne) <= kSliceWords;
     if (in_lds) {
-        for (uint32_t j = threadIdx.x; j < ns; j += blockDim.x) slice[j] = bs[s_lo + j];
-        for (uint32_t j = threadIdx.x; j < ne; j += blockDim.x) slice[ns + j] = be[e_lo + j];
+        for (uint32_t j = threadIdx.x; j < ns; j += blockDim.x) slice[skew(j)] = bs[s_lo + j];
+        for (uint32_t j = threadIdx.x; j < ne; j += blockDim.x) slice[eo + skew(j)] = be[e_lo + j];
     }
     __syncthreads();
-    if (in_lds)
-        bin_count_region<true>(slice, ns, slice + ns, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb, acc);
+    // per-step sums fit 32 bits when 64 counts of at most n cannot reach 2^32
+    const bool narrow = n < (1u << 26);
+    if (in_lds && narrow)
+        bin_count_region<true, uint32_t>(slice, ns, slice + eo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb, acc);
+    else if (in_lds)
+        bin_count_region<true, uint64_t>(slice, ns, slice + eo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb, acc);
+    else if (narrow)
+        bin_count_region<false, uint32_t>(bs + s_lo, ns, be + e_lo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb,
+                                          acc);
     else
-        bin_count_region<false>(bs + s_lo, ns, be + e_lo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb, acc);
+        bin_count_region<false, uint64_t>(bs + s_lo, ns, be + e_lo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb,
+                                          acc);
     __syncthreads();
     if (threadIdx.x < nb) partial[(uint64_t)r * nb + threadIdx.x] = acc[threadIdx.x];
 }
