@@ -287,7 +287,8 @@ int bits_mc_pvalue(const bits_ref *ref, const uint32_t *d_a_start, const uint32_
 /* Workspace bytes of bits_mc_binned for na queries (na < 2^32) against a
  * reference of n intervals on the genome chrom_len[n_chrom], with `batch`
  * shuffles per pass (1 <= batch <= BITS_MC_BIN_MAX_BATCH): the query table
- * of bits_mc_workspace; 28 bytes per cell of the genome (cells of 2^S bp,
+ * of bits_mc_workspace plus 8 bytes per query; about 24 bytes per cell of
+ * the genome (cells of 2^S bp,
  * S >= 10 the least that leaves at most 8192 cells in every chromosome);
  * 16 + 16 * batch bytes per region (at most n_chrom + 2n / 8192 regions);
  * and 8 * batch * na bytes of placement records.  BITS_E_CHROM if the

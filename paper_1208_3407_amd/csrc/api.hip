@@ -412,7 +412,7 @@ int bits_mc_pvalue(const bits_ref* ref, const uint32_t* d_a_start, const uint32_
 namespace {
 struct BinWsLayout {
     BinLayout L;
-    size_t table, rs, re, flag, offsets, tiles, cell_region, desc, seg_start, seg_cnt, partial, recs, total;
+    size_t table, rs, re, flag, offsets, tiles, cell_region, desc, seg_start, seg_cnt, partial, packed, recs, total;
 };
 
 bool bin_ws_layout(uint64_t na, uint64_t n, const uint32_t* chrom_len, uint32_t n_chrom, uint32_t batch,
@@ -432,6 +432,7 @@ bool bin_ws_layout(uint64_t na, uint64_t n, const uint32_t* chrom_len, uint32_t 
     W->seg_start = o; o = align256(o + (size_t)batch * nr * sizeof(uint32_t));
     W->seg_cnt = o; o = align256(o + (size_t)batch * nr * sizeof(uint32_t));
     W->partial = o; o = align256(o + (size_t)batch * nr * sizeof(uint64_t));
+    W->packed = o; o = align256(o + (size_t)na * 8);
     W->recs = o; o = align256(o + (size_t)batch * na * 8);
     W->total = o;
     return true;
@@ -498,12 +499,15 @@ int bits_mc_binned(const bits_ref* ref, const uint32_t* d_a_start, const uint32_
         bw.seg_cnt = (uint32_t*)(w + W.seg_cnt);
         bw.partial = (unsigned long long*)(w + W.partial);
         bw.recs = w + W.recs;
+        bw.packed = w + W.packed;
         bw.nreg_max = (uint32_t)W.L.nreg_max;
         BITS_CHECK_HIP(launch_mc_prepare(d_a_start, d_a_end, na, chrom_len, n_chrom, tab, ref->status, s));
         BITS_CHECK_HIP(launch_mc(make_search_args(ref, cfg), cfg, d_a_start, d_a_end, tab, na, seed, s0, 0, totals,
                                  obs, s));
-        if (W.L.ncells && ns)   // a genome of length 0 holds no legal placement
+        if (W.L.ncells && ns) {   // a genome of length 0 holds no legal placement
             BITS_CHECK_HIP(launch_bin_regions(chrom_len, n_chrom, ref->bs, ref->be, ref->n, bw, ref->status, s));
+            BITS_CHECK_HIP(launch_bin_pack(tab, na, bw, s));
+        }
         for (uint64_t sb = s0; W.L.ncells && sb < s1; sb += batch) {
             const uint32_t nb = (uint32_t)((s1 - sb) < batch ? (s1 - sb) : batch);
             BITS_CHECK_HIP(launch_bin_batch(chrom_len, n_chrom, tab, na, ref->bs, ref->be, ref->n, seed, sb, nb, bw,

@@ -186,14 +186,23 @@ __global__ void __launch_bounds__(256) k_bin_regions(BinGeom g, const uint32_t* 
     }
 }
 
+// The per-query table the binning kernel reads: {input index, length}, the
+// length 0 for a query outside its chromosome (span 0).  A query's legal
+// starts follow from its chromosome's length: span = len_k - L + 1.
+__global__ void __launch_bounds__(256) k_bin_pack(const uint32_t* __restrict__ span, const uint32_t* __restrict__ len,
+                                                  const uint32_t* __restrict__ idx, uint64_t na,
+                                                  uint2* __restrict__ packed) {
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < na; p += (uint64_t)gridDim.x * blockDim.x)
+        packed[p] = make_uint2(idx[p], span[p] ? len[p] : 0u);
+}
+
 // Binning of shuffles [sb, sb + nb): workgroup (k, s) makes the placements of
 // chromosome k's queries (table positions [cursor[k] - hist[k], cursor[k]))
 // in shuffle sb + s, counts them per region, writes the segment table of
 // (s, every region of k), and writes the records {start, end} in region
 // order to recs[s * na + table position range].
 __global__ void __launch_bounds__(kBinThreads) k_bin_place(
-    BinGeom g, const uint32_t* __restrict__ off, const uint32_t* __restrict__ span, const uint32_t* __restrict__ len,
-    const uint32_t* __restrict__ idx, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ cursor,
+    BinGeom g, const uint2* __restrict__ packed, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ cursor,
     uint64_t na, uint64_t seed, uint64_t sb, uint32_t nb, const uint32_t* __restrict__ cell_region,
     const uint64_t* __restrict__ offsets, uint32_t nreg_max, uint32_t* __restrict__ seg_start,
     uint32_t* __restrict__ seg_cnt, uint2* __restrict__ recs) {
@@ -213,13 +222,13 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_place(
     for (uint32_t j = threadIdx.x; j < nr; j += blockDim.x) h[j] = 0u;
     __syncthreads();
     const uint32_t g1 = cursor[k], g0 = g1 - hist[k];
-    const uint32_t ok = g.off[k], sh = g.shift;
+    const uint32_t ok = g.off[k], sh = g.shift, clen = g.off[k + 1] - g.off[k];
     const uint64_t gs = (sb + s) * na;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     for (uint32_t p = g0 + threadIdx.x; p < g1; p += blockDim.x) {
-        const uint32_t sp = span[p];
-        if (!sp) continue;
-        const uint32_t st = mc_place(gs + idx[p], k0, k1, off[p], sp);
+        const uint2 q = packed[p];
+        if (!q.y) continue;
+        const uint32_t st = mc_place(gs + q.x, k0, k1, ok, clen - q.y + 1u);
         const uint32_t lr = cr[(st - ok) >> sh];
         if (lr < nr) atomicAdd(&h[lr], 1u);
     }
@@ -233,13 +242,13 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_place(
     __syncthreads();
     uint2* out = recs + (uint64_t)s * na;
     for (uint32_t p = g0 + threadIdx.x; p < g1; p += blockDim.x) {
-        const uint32_t sp = span[p];
-        if (!sp) continue;
-        const uint32_t st = mc_place(gs + idx[p], k0, k1, off[p], sp);
+        const uint2 q = packed[p];
+        if (!q.y) continue;
+        const uint32_t st = mc_place(gs + q.x, k0, k1, ok, clen - q.y + 1u);
         const uint32_t lr = cr[(st - ok) >> sh];
         if (lr >= nr) continue;
         const uint32_t at = atomicAdd(&h[lr], 1u);
-        out[g0 + at] = make_uint2(st, st + (len[p] - 1u));
+        out[g0 + at] = make_uint2(st, st + (q.y - 1u));
     }
 }
 
@@ -425,6 +434,14 @@ bool bin_layout(const uint32_t* chrom_len, uint32_t n_chrom, uint64_t n, BinLayo
     return true;
 }
 
+hipError_t launch_bin_pack(const McTable& tab, uint64_t na, const BinWs& w, hipStream_t s) {
+    if (!na) return hipSuccess;
+    const uint32_t gr = (uint32_t)std::min<uint64_t>((na + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_bin_pack, dim3(gr), dim3(256), 0, s, tab.span, tab.len, tab.idx, na,
+                       reinterpret_cast<uint2*>(w.packed));
+    return hipGetLastError();
+}
+
 hipError_t launch_bin_regions(const uint32_t* chrom_len, uint32_t n_chrom, const uint32_t* bs, const uint32_t* be,
                               uint32_t n, const BinWs& w, uint32_t* status, hipStream_t s) {
     BinGeom g;
@@ -448,9 +465,9 @@ hipError_t launch_bin_batch(const uint32_t* chrom_len, uint32_t n_chrom, const M
     if (!bin_geometry(chrom_len, n_chrom, &g)) return hipErrorInvalidValue;
     if (nb == 0 || nb > BITS_MC_BIN_MAX_BATCH) return hipErrorInvalidValue;
     const uint32_t ncells = g.cb[n_chrom];
-    hipLaunchKernelGGL(k_bin_place, dim3(n_chrom * nb), dim3(kBinThreads), 0, s, g, tab.off, tab.span, tab.len,
-                       tab.idx, tab.hist, tab.cursor, na, seed, sb, nb, w.cell_region, w.offsets, w.nreg_max,
-                       w.seg_start, w.seg_cnt, reinterpret_cast<uint2*>(w.recs));
+    hipLaunchKernelGGL(k_bin_place, dim3(n_chrom * nb), dim3(kBinThreads), 0, s, g,
+                       reinterpret_cast<const uint2*>(w.packed), tab.hist, tab.cursor, na, seed, sb, nb,
+                       w.cell_region, w.offsets, w.nreg_max, w.seg_start, w.seg_cnt, reinterpret_cast<uint2*>(w.recs));
     hipLaunchKernelGGL(k_bin_search, dim3(w.nreg_max), dim3(kBinThreads), 0, s, bs, be, n,
                        reinterpret_cast<const RegionDesc*>(w.desc), w.offsets + ncells, w.seg_start, w.seg_cnt,
                        w.nreg_max, nb, reinterpret_cast<const uint2*>(w.recs), na, w.partial);

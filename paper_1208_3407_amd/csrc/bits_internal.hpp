@@ -222,8 +222,10 @@ struct BinWs {                    // device buffers, carved from the caller's wo
     uint32_t *seg_start, *seg_cnt;    // [batch][nreg_max]
     unsigned long long* partial;      // [nreg_max][batch]
     void* recs;                       // [batch][na] {start, end}
+    void* packed;                     // [na] {input index, length or 0}
     uint32_t nreg_max;
 };
+hipError_t launch_bin_pack(const McTable& tab, uint64_t na, const BinWs& w, hipStream_t s);
 hipError_t launch_bin_regions(const uint32_t* chrom_len, uint32_t n_chrom, const uint32_t* bs, const uint32_t* be,
                               uint32_t n, const BinWs& w, uint32_t* status, hipStream_t s);
 // Shuffles [sb, sb + nb) (absolute indices); totals points at shuffle sb's slot.
