@@ -9,8 +9,9 @@ One step is one pass of the whole hot path on inputs already resident in
 HBM (chromosome-local coordinates):
   projection of A and B -> on-device radix sort of B_S and B_E, Eytzinger top
   trees, learned CDF index trained on the device -> per-query counts of all
-  of A through the learned index -> 1,000 Monte-Carlo shuffles (one
-  persistent launch) with observed total and tail counts.
+  of A through the learned index -> 1,000 Monte-Carlo shuffles binned by
+  genome region and counted in LDS (one pass of 1,000 shuffles), with the
+  observed total and tail counts.
 value = A-intervals counted per second over the step (50M queries + 1,000 x
 1M shuffled queries per step).  Printed as one JSON line.
 """
@@ -32,18 +33,22 @@ N_MC = 1_000_000
 N_SHUF = 1_000
 N_ENUM = 10_000_000   # A-intervals enumerated against the full B (outside the timed region)
 MC_SEED = 7
-# Algorithmic HBM bytes per Monte-Carlo evaluation (one shuffled A-interval):
-# the learned search through the line heads reads exactly one 128-byte line
-# of B_S and one of B_E (leaf records and line heads are L2-resident); the
-# 16-byte query-table entry is read once per chunk of up to 64 shuffles.
+MC_BATCH = 1000       # shuffles per pass of the binned Monte-Carlo path (8.2 GB workspace at 1e6 queries)
+# Algorithmic HBM bytes per placement (one shuffled A-interval) of the binned Monte-Carlo kernels:
+#   k_bin_place   reads the query's 8-byte {index, length} entry, writes its 8-byte {start, end} record;
+#   k_bin_search  reads the record back (8 bytes); each region also stages its slices of B_S and B_E
+#                 once per pass (4 bytes per key of both arrays, added per pass below).
+BYTES_PER_PLACEMENT = {"k_bin_place": 16.0, "k_bin_search": 8.0}
+# The query-ordered learned path (compared outside the timed region): the search through the line
+# heads reads exactly one 128-byte line of B_S and one of B_E per evaluation.
 BYTES_PER_EVAL_LEARNED = 256.0
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_mc_learned_w4.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_bin_w4.json")
 # launch shapes the autotuner picked on MI355X for this workload (used with --no-autotune)
 RECORDED_LEARNED = {"block": 512, "qpl": 1, "depth": 0, "grid": 0, "path": 2}
 RECORDED_PLAIN = {"block": 256, "qpl": 1, "depth": 13, "grid": 0, "path": 1}
 RECORDED_MC = {"block": 1024, "qpl": 1, "depth": 0, "grid": 0, "path": 2}
-KERNEL_SOURCES = ["paper_1208_3407_amd/csrc/search.hip", "paper_1208_3407_amd/csrc/bits_internal.hpp"]
+KERNEL_SOURCES = ["paper_1208_3407_amd/csrc/binned.hip", "paper_1208_3407_amd/csrc/bits_internal.hpp"]
 
 
 def log(*a):
@@ -58,17 +63,17 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(evals_per_launch):
-    """HBM bytes per launch of the dominant kernel from the committed counter
+def load_traffic(kernel, placements_per_launch):
+    """HBM bytes per launch of a binned kernel from the committed counter
     summary, if it was taken on the current kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != kernel_hash():
+    if t.get("kernel_hash") != kernel_hash() or kernel not in t.get("bytes_per_placement", {}):
         return None
-    return float(t["bytes_per_eval"]) * evals_per_launch
+    return float(t["bytes_per_placement"][kernel]) * placements_per_launch
 
 
 def tune_mc(bits, ref, a_s, a_e, lengths, ws):
@@ -182,6 +187,7 @@ def main():
     ref = bits.bits_ref_init(N_B, 13, learned=True)
     ws = bits._scratch(bits.bits_sort_ref_workspace(N_B), dev)
     mc_ws = bits._scratch(bits.bits_mc_workspace(N_MC), dev)
+    bin_ws = bits._scratch(bits.bits_mc_binned_workspace(N_MC, N_B, lengths, MC_BATCH), dev)
     counts = torch.empty(N_A, dtype=torch.uint32, device=dev)
     total = torch.empty(1, dtype=torch.uint64, device=dev)
     mc_out = bits.MCResult(torch.empty(N_SHUF, dtype=torch.uint64, device=dev),
@@ -216,8 +222,8 @@ def main():
         bits.bits_count_per_query(ref, a_s, a_e, launch=lp_learned, counts=counts, total=total)
         if record:
             ev[2].record()
-        bits.bits_mc_pvalue(ref, a_s[:N_MC], a_e[:N_MC], lengths, MC_SEED, 0, N_SHUF, launch=lp_mc,
-                            workspace=mc_ws, out=mc_out)
+        bits.bits_mc_binned(ref, a_s[:N_MC], a_e[:N_MC], lengths, MC_SEED, 0, N_SHUF, batch=MC_BATCH,
+                            launch=lp_mc, workspace=bin_ws, out=mc_out)
         if record:
             ev[3].record()
         return a_s, a_e
@@ -226,6 +232,8 @@ def main():
         step(False)
     torch.cuda.synchronize()
     phase = {"setup_ms": [], "count_ms": [], "mc_ms": []}
+    stages = {"place": [], "search": [], "reduce": []}
+    bits.bits_mc_binned_timing(True)    # HIP events around the binned kernels, on the stream they run on
     t_start = time.perf_counter()
     for _ in range(args.steps):
         step(True)
@@ -233,8 +241,11 @@ def main():
         phase["setup_ms"].append(ev[0].elapsed_time(ev[1]))
         phase["count_ms"].append(ev[1].elapsed_time(ev[2]))
         phase["mc_ms"].append(ev[2].elapsed_time(ev[3]))
+        for k, v in bits.bits_mc_binned_stage_ms().items():
+            stages[k].append(v)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    bits.bits_mc_binned_timing(False)
     ms_per_step = t_total * 1e3 / args.steps
     evals = N_A + N_SHUF * N_MC
     value = evals / (ms_per_step / 1e3)
@@ -263,7 +274,15 @@ def main():
                              torch.empty(1, dtype=torch.uint64, device=dev))
     t_mc_plain = timed(lambda: bits.bits_mc_pvalue(ref, a_s[:N_MC], a_e[:N_MC], lengths, MC_SEED, 0, N_SHUF,
                                                    launch=lp_plain, workspace=mc_ws, out=mc_plain), reps=1)
+    mc_learned = bits.MCResult(torch.empty(N_SHUF, dtype=torch.uint64, device=dev),
+                               torch.empty(1, dtype=torch.uint64, device=dev),
+                               torch.empty(1, dtype=torch.uint64, device=dev),
+                               torch.empty(1, dtype=torch.uint64, device=dev))
+    t_mc_learned = timed(lambda: bits.bits_mc_pvalue(ref, a_s[:N_MC], a_e[:N_MC], lengths, MC_SEED, 0, N_SHUF,
+                                                     launch=lp_mc, workspace=mc_ws, out=mc_learned), reps=2)
     agree = (plain_total == learned_total) and np.array_equal(mc_plain.totals.cpu().numpy(), mc_totals)
+    binned_agree = (np.array_equal(mc_learned.totals.cpu().numpy(), mc_totals)
+                    and int(mc_learned.observed.item()) == int(mc_out.observed.item()))
     info = bits.bits_rmi_info(ref)
 
     # enumeration (sub-problem 4) of the first N_ENUM A-intervals against B, outside the timed region
@@ -325,9 +344,17 @@ def main():
     del ref_po, po
 
     mc_avg = float(np.mean(phase["mc_ms"]))
-    mc_evals = N_SHUF * N_MC + N_MC
-    achieved = BYTES_PER_EVAL_LEARNED * mc_evals / (mc_avg / 1e3) / 1e9
-    traffic = load_traffic(N_SHUF * N_MC)
+    stage_ms = {k: float(np.mean(v)) for k, v in stages.items()}
+    # dominant binned kernel of the step and its algorithmic bytes per launch (one pass of MC_BATCH
+    # shuffles; the step runs N_SHUF / MC_BATCH passes)
+    passes = (N_SHUF + MC_BATCH - 1) // MC_BATCH
+    placements = N_SHUF * N_MC // passes
+    dom = "k_bin_place" if stage_ms["place"] >= stage_ms["search"] else "k_bin_search"
+    dom_ms = (stage_ms["place"] if dom == "k_bin_place" else stage_ms["search"]) / passes
+    dom_bytes = BYTES_PER_PLACEMENT[dom] * placements + (8.0 * N_B if dom == "k_bin_search" else 0.0)
+    achieved = dom_bytes / (dom_ms / 1e3) / 1e9
+    traffic = load_traffic(dom, placements)
+    learned_achieved = BYTES_PER_EVAL_LEARNED * N_SHUF * N_MC / (t_mc_learned / 1e3) / 1e9
     result = {
         "metric": "A-intervals counted/s (learned vs binary-search index); MC shuffles/s",
         "value": value,
@@ -344,23 +371,31 @@ def main():
         "config": {"workload": "learned index at scale: B=5e7 clustered, A=5e7 uniform, MC 1000 x 1e6 "
                                "(24-chromosome genome)",
                    "n_b": N_B, "n_a": N_A, "mc_queries": N_MC, "mc_shuffles": N_SHUF, "train_epochs": args.epochs,
-                   "launch_learned": lp_learned, "launch_plain": lp_plain, "launch_mc": lp_mc},
+                   "launch_learned": lp_learned, "launch_plain": lp_plain,
+                   "mc": {"path": "binned by genome region", "batch": MC_BATCH, "observed_launch": lp_mc}},
         "phases_ms": {k: float(np.mean(v)) for k, v in phase.items()},
+        "mc_stage_ms": stage_ms,
         "count_learned_aps": N_A / (t_learned / 1e3),
         "count_plain_aps": N_A / (t_plain / 1e3),
         "learned_speedup": t_plain / t_learned,
         "mc_shuffles_per_s": N_SHUF / (mc_avg / 1e3),
+        "mc_shuffles_per_s_learned": N_SHUF / (t_mc_learned / 1e3),
         "mc_shuffles_per_s_plain": N_SHUF / (t_mc_plain / 1e3),
         "learned_equals_plain": bool(agree),
+        "binned_equals_learned": bool(binned_agree),
         "rmi": info,
         "enumeration": enumeration,
         "significance": significance,
         "paper_orientation": paper_orientation,
         "status": status,
-        "roofline": {"bound": "hbm", "kernel": "k_mc_sorted (learned-index Monte-Carlo shuffles)",
+        "roofline": {"bound": "hbm", "kernel": dom + " (Monte-Carlo shuffles binned by genome region)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "bytes_per_eval_model": BYTES_PER_EVAL_LEARNED,
-                     "launch_ms": mc_avg},
+                     "traffic": traffic, "bytes_per_placement_model": BYTES_PER_PLACEMENT[dom],
+                     "placements_per_launch": placements, "launch_ms": dom_ms},
+        "roofline_learned_mc": {"bound": "hbm", "kernel": "k_mc_sorted (query-ordered learned-index Monte-Carlo, "
+                                "outside the timed region)", "achieved": learned_achieved, "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": learned_achieved / HBM_PEAK_GBS,
+                                "bytes_per_eval_model": BYTES_PER_EVAL_LEARNED, "call_ms": t_mc_learned},
     }
     if not args.no_cpu_baseline:
         threads = max(1, min(16, os.cpu_count() or 1))

@@ -320,6 +320,17 @@ int bits_mc_binned(const bits_ref *ref, const uint32_t *d_a_start, const uint32_
                    uint32_t batch, void *d_ws, size_t ws_bytes, uint64_t *d_totals, uint64_t *d_observed,
                    uint64_t *d_n_ge, uint64_t *d_n_le, const bits_launch *launch, void *stream);
 
+/* Stage timing of bits_mc_binned, for profiling.  With timing on
+ * (enable != 0; off by default), each later bits_mc_binned call records HIP
+ * events on its stream around every pass's binning, search and reduction
+ * kernels (recording only: nothing inside the call waits).
+ * bits_mc_binned_stage_ms waits for the last call's events and writes the
+ * summed milliseconds of its binning, search and reduction kernels to
+ * ms[0], ms[1], ms[2] (zeros if nothing was recorded).  Calls that overlap
+ * in time share one record. */
+int bits_mc_binned_timing(int enable);
+int bits_mc_binned_stage_ms(float *ms);
+
 /* Workspace bytes of bits_mc_resort for |B| = nb and `batch` rounds per
  * sort launch (1 <= batch <= 4096): 16 bytes per interval of B, 16 bytes per
  * interval per round of the batch, and the segmented sort's workspace. */

@@ -105,6 +105,8 @@ def _load():
         "bits_scan_counts": ([_vp, _u64, _vp, _vp, _sz, _vp], ctypes.c_int),
         "bits_mc_resort_workspace": ([_u64, _u32, P(_sz)], ctypes.c_int),
         "bits_mc_binned_workspace": ([_u64, _u64, P(_u32), _u32, _u32, P(_sz)], ctypes.c_int),
+        "bits_mc_binned_timing": ([ctypes.c_int], ctypes.c_int),
+        "bits_mc_binned_stage_ms": ([P(ctypes.c_float)], ctypes.c_int),
         "bits_mc_binned": ([P(bits_ref), _vp, _vp, _u64, P(_u32), _u32, _u64, _u64, _u64, _u32, _vp, _sz, _vp, _vp,
                             _vp, _vp, P(bits_launch), _vp], ctypes.c_int),
         "bits_mc_resort": ([_vp, _vp, _u64, _vp, _vp, _u64, P(_u32), _u32, _u64, _u64, _u64, _u32, _vp, _sz, _vp,
@@ -439,6 +441,17 @@ def bits_mc_binned(ref: Ref, a_start, a_end, chrom_len, seed: int, s0: int, s1: 
                                ctypes.c_void_p(out.n_le.data_ptr()), _lp(launch), _stream(stream)), "bits_mc_binned")
     out._keepalive = workspace
     return out
+
+
+def bits_mc_binned_timing(enable: bool) -> None:
+    _check(_lib.bits_mc_binned_timing(1 if enable else 0), "bits_mc_binned_timing")
+
+
+def bits_mc_binned_stage_ms() -> dict:
+    """Device milliseconds of the last timed bits_mc_binned call, per stage."""
+    ms = (ctypes.c_float * 3)()
+    _check(_lib.bits_mc_binned_stage_ms(ms), "bits_mc_binned_stage_ms")
+    return {"place": float(ms[0]), "search": float(ms[1]), "reduce": float(ms[2])}
 
 
 def bits_mc_resort_workspace(nb: int, batch: int) -> int:

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -410,6 +411,46 @@ int bits_mc_pvalue(const bits_ref* ref, const uint32_t* d_a_start, const uint32_
 // ---------------------------------------------------------------- Monte-Carlo binned by region
 
 namespace {
+// Stage timing of bits_mc_binned (off unless bits_mc_binned_timing(1)): four
+// events per pass of the last call, created on first use and kept.
+struct BinTiming {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> ev;   // 4 per pass
+    size_t used = 0;              // events recorded by the last call
+};
+BinTiming& bin_timing() {
+    static BinTiming t;
+    return t;
+}
+}  // namespace
+
+int bits_mc_binned_timing(int enable) {
+    BinTiming& t = bin_timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    t.on = enable != 0;
+    t.used = 0;
+    return BITS_OK;
+}
+
+int bits_mc_binned_stage_ms(float* ms) {
+    if (!ms) return BITS_E_ARG;
+    BinTiming& t = bin_timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    ms[0] = ms[1] = ms[2] = 0.0f;
+    if (!t.used) return BITS_OK;
+    BITS_CHECK_HIP(hipEventSynchronize(t.ev[t.used - 1]));
+    for (size_t b = 0; b + 4 <= t.used; b += 4) {
+        for (int k = 0; k < 3; ++k) {
+            float x = 0.0f;
+            BITS_CHECK_HIP(hipEventElapsedTime(&x, t.ev[b + k], t.ev[b + k + 1]));
+            ms[k] += x;
+        }
+    }
+    return BITS_OK;
+}
+
+namespace {
 struct BinWsLayout {
     BinLayout L;
     size_t table, rs, re, flag, offsets, tiles, cell_region, desc, seg_start, seg_cnt, partial, packed, recs, total;
@@ -508,10 +549,23 @@ int bits_mc_binned(const bits_ref* ref, const uint32_t* d_a_start, const uint32_
             BITS_CHECK_HIP(launch_bin_regions(chrom_len, n_chrom, ref->bs, ref->be, ref->n, bw, ref->status, s));
             BITS_CHECK_HIP(launch_bin_pack(tab, na, bw, s));
         }
+        BinTiming& tm = bin_timing();
+        std::unique_lock<std::mutex> tl(tm.mu);
+        tm.used = 0;
         for (uint64_t sb = s0; W.L.ncells && sb < s1; sb += batch) {
             const uint32_t nb = (uint32_t)((s1 - sb) < batch ? (s1 - sb) : batch);
+            hipEvent_t* ev = nullptr;
+            if (tm.on) {
+                while (tm.ev.size() < tm.used + 4) {
+                    hipEvent_t e;
+                    BITS_CHECK_HIP(hipEventCreate(&e));
+                    tm.ev.push_back(e);
+                }
+                ev = tm.ev.data() + tm.used;
+                tm.used += 4;
+            }
             BITS_CHECK_HIP(launch_bin_batch(chrom_len, n_chrom, tab, na, ref->bs, ref->be, ref->n, seed, sb, nb, bw,
-                                            totals + (sb - s0), s));
+                                            totals + (sb - s0), s, ev));
         }
     }
     BITS_CHECK_HIP(launch_mc_tail(totals, ns, obs, (unsigned long long*)d_n_ge, (unsigned long long*)d_n_le, s));

@@ -460,21 +460,28 @@ hipError_t launch_bin_regions(const uint32_t* chrom_len, uint32_t n_chrom, const
 
 hipError_t launch_bin_batch(const uint32_t* chrom_len, uint32_t n_chrom, const McTable& tab, uint64_t na,
                             const uint32_t* bs, const uint32_t* be, uint32_t n, uint64_t seed, uint64_t sb,
-                            uint32_t nb, const BinWs& w, unsigned long long* totals, hipStream_t s) {
+                            uint32_t nb, const BinWs& w, unsigned long long* totals, hipStream_t s,
+                            hipEvent_t* ev) {
     BinGeom g;
     if (!bin_geometry(chrom_len, n_chrom, &g)) return hipErrorInvalidValue;
     if (nb == 0 || nb > BITS_MC_BIN_MAX_BATCH) return hipErrorInvalidValue;
     const uint32_t ncells = g.cb[n_chrom];
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_place, dim3(n_chrom * nb), dim3(kBinThreads), 0, s, g,
                        reinterpret_cast<const uint2*>(w.packed), tab.hist, tab.cursor, na, seed, sb, nb,
                        w.cell_region, w.offsets, w.nreg_max, w.seg_start, w.seg_cnt, reinterpret_cast<uint2*>(w.recs));
+    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_search, dim3(w.nreg_max), dim3(kBinThreads), 0, s, bs, be, n,
                        reinterpret_cast<const RegionDesc*>(w.desc), w.offsets + ncells, w.seg_start, w.seg_cnt,
                        w.nreg_max, nb, reinterpret_cast<const uint2*>(w.recs), na, w.partial);
+    if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
     const uint32_t gy = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(w.nreg_max / 64, 1), 256);
     hipLaunchKernelGGL(k_bin_reduce, dim3((nb + 255) / 256, gy), dim3(256), 0, s, w.partial, w.offsets + ncells, nb,
                        totals);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
 }  // namespace bits

@@ -231,7 +231,8 @@ hipError_t launch_bin_regions(const uint32_t* chrom_len, uint32_t n_chrom, const
 // Shuffles [sb, sb + nb) (absolute indices); totals points at shuffle sb's slot.
 hipError_t launch_bin_batch(const uint32_t* chrom_len, uint32_t n_chrom, const McTable& tab, uint64_t na,
                             const uint32_t* bs, const uint32_t* be, uint32_t n, uint64_t seed, uint64_t sb,
-                            uint32_t nb, const BinWs& w, unsigned long long* totals, hipStream_t s);
+                            uint32_t nb, const BinWs& w, unsigned long long* totals, hipStream_t s,
+                            hipEvent_t* ev = nullptr);   // ev[4]: before binning, search, reduction, after
 hipError_t launch_mc_tail(const unsigned long long* totals, uint64_t nshuf, const unsigned long long* observed,
                           unsigned long long* n_ge, unsigned long long* n_le, hipStream_t s);
 hipError_t launch_project(const uint32_t* chrom_len, uint32_t n_chrom, const uint32_t* chrom,
