@@ -146,4 +146,35 @@ def test_w4_full_learned_vs_plain_and_sampled():
     obs = oracle.count_sorted(sbs, sbe, oa_s[:nmc], oa_e[:nmc], threads=THREADS, per_query=False)[1]
     assert int(down(mc.observed)[0]) == obs
     assert (int(down(mc.n_ge)[0]), int(down(mc.n_le)[0])) == oracle.mc_tail(T, obs)
+    # the region-binned path in bench.py's configuration (one pass of 1000 shuffles)
+    from bench import MC_BATCH
+    mb = bits.bits_mc_binned(ref, a_s[:nmc], a_e[:nmc], lengths, datagen.MC_SEED, 0, 1000, batch=MC_BATCH,
+                             launch=RECORDED_MC)
+    assert np.array_equal(down(mb.totals), T)
+    assert int(down(mb.observed)[0]) == obs
+    assert (int(down(mb.n_ge)[0]), int(down(mb.n_le)[0])) == oracle.mc_tail(T, obs)
+    assert bits.bits_get_status(ref) == 0
+
+
+def test_binned_reference_past_2_pow_26():
+    """A reference of 7e7 intervals (64 counts of n can pass 2^32, so the search
+    kernel sums each 64-record step in 64 bits): the binned totals equal the
+    query-ordered plain path's, and sampled shuffles equal the oracle's."""
+    note("case: binned, n = 7e7")
+    lengths, A, B = datagen.w4_sets(seed=3, n_a=20_000, n_b=70_000_000)
+    a_s, a_e = proj(lengths, A)
+    b_s, b_e = proj(lengths, B)
+    ref = bits.bits_sort_ref(b_s, b_e)
+    mb = bits.bits_mc_binned(ref, a_s, a_e, lengths, datagen.MC_SEED, 0, 12, batch=5)
+    mp = bits.bits_mc_pvalue(ref, a_s, a_e, lengths, datagen.MC_SEED, 0, 12, launch=RECORDED_PLAIN)
+    T = down(mb.totals).copy()
+    assert np.array_equal(T, down(mp.totals))
+    assert int(down(mb.observed)[0]) == int(down(mp.observed)[0])
+    ob_s, ob_e = oracle.project(lengths, B.chrom, B.start, B.end)
+    del B
+    sbs, sbe = oracle.sort_u32(ob_s), oracle.sort_u32(ob_e)
+    oa_s, oa_e = oracle.project(lengths, A.chrom, A.start, A.end)
+    prep = oracle.mc_prepare(lengths, oa_s, oa_e)
+    for s in (0, 11):
+        assert int(T[s]) == int(oracle.mc_totals(sbs, sbe, prep, datagen.MC_SEED, s, s + 1, threads=THREADS)[0]), s
     assert bits.bits_get_status(ref) == 0
