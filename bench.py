@@ -391,7 +391,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom + " (Monte-Carlo shuffles binned by genome region)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_placement_model": BYTES_PER_PLACEMENT[dom],
-                     "placements_per_launch": placements, "launch_ms": dom_ms},
+                     "placements_per_launch": placements, "launch_ms": dom_ms,
+                     "limiter": ("LDS and VALU issue (LDS busy and bank-conflict share in "
+                                 "profiles/k_bin_w4_lds_counters.md)" if dom == "k_bin_search" else
+                                 "partly written lines of the scattered records (profiles/k_bin_w4_hbm_counters.md)")},
         "roofline_learned_mc": {"bound": "hbm", "kernel": "k_mc_sorted (query-ordered learned-index Monte-Carlo, "
                                 "outside the timed region)", "achieved": learned_achieved, "peak": HBM_PEAK_GBS,
                                 "unit": "GB/s", "frac": learned_achieved / HBM_PEAK_GBS,
