@@ -58,25 +58,21 @@ __device__ __forceinline__ uint32_t chrom_of_cell(const BinGeom& g, uint32_t c) 
     return lo;
 }
 
-// Word of element j of a slice staged in LDS with one spare word after every
-// 32: the bisection's probes sit at power-of-two distances, which without
-// the skew would fall into a few of the 32 LDS banks.
-__host__ __device__ constexpr uint32_t skew(uint32_t j) { return j + (j >> 5); }
-__host__ __device__ constexpr uint64_t skewed_len(uint64_t m) { return m + (m >> 5) + 1; }
-
-// #{K[0..m) < x} (STRICT) or #{K[0..m) <= x} (K skewed when SKEW); the same
-// number of steps for every lane at a given m.
-template <bool STRICT, bool SKEW = false>
+// #{K[0..m) < x} (STRICT) or #{K[0..m) <= x}; the same number of steps for
+// every lane at a given m.  (Staging the slices with a spare word per 32
+// keys spreads the probes over more LDS banks, but its two extra VALU
+// operations per probe cost more than the conflicts it saves.)
+template <bool STRICT>
 __device__ __forceinline__ uint32_t rank_in(const uint32_t* K, uint32_t m, uint32_t x) {
     if (m == 0) return 0;
     uint32_t base = 0, len = m;
     while (len > 1) {
         const uint32_t half = len >> 1;
-        const uint32_t k = K[SKEW ? skew(base + half) : base + half];
+        const uint32_t k = K[base + half];
         if (STRICT ? (k < x) : (k <= x)) base += half;
         len -= half;
     }
-    const uint32_t k = K[SKEW ? skew(base) : base];
+    const uint32_t k = K[base];
     return base + (STRICT ? (k < x) : (k <= x));
 }
 
@@ -274,8 +270,7 @@ __device__ __forceinline__ void wave_segment_add(uint32_t key, T v, bool valid, 
 }
 
 // The placements of one region, counted against slices S = B_S[s_lo, s_lo + ns)
-// and E = B_E[e_lo, e_lo + ne) (skewed in LDS, or plain in HBM for an
-// oversize region).  Each wave takes a contiguous range of the region's
+// and E = B_E[e_lo, e_lo + ne) (in LDS, or in HBM for an oversize region).  Each wave takes a contiguous range of the region's
 // records, 64 per step; records are grouped by shuffle (pre[s] = first
 // record of shuffle s), so a wave tracks its shuffle by a forward scan and
 // adds per-shuffle sums with wave_segment_add.
@@ -309,10 +304,10 @@ __device__ __forceinline__ void bin_count_region(const uint32_t* S, uint32_t ns,
             if (r.y == 0xFFFFFFFFu) {
                 first = n;
             } else {
-                const uint32_t c = rank_in<false, LDS>(S, ns, r.y);
+                const uint32_t c = rank_in<false>(S, ns, r.y);
                 first = (c == ns && s_end < n) ? gallop_le(bs, n, s_end, r.y) : s_lo + c;
             }
-            v = (T)(first - (e_lo + rank_in<true, LDS>(E, ne, r.x)));
+            v = (T)(first - (e_lo + rank_in<true>(E, ne, r.x)));
         }
         wave_segment_add<T>(valid ? sl : 0xFFFFFFFFu, v, valid, acc);
         sw = __shfl(sl, kWave - 1);
@@ -360,11 +355,11 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_search(
         if (threadIdx.x < nb) pre[threadIdx.x] = before + x - cnt;
         if (threadIdx.x == nb - 1) pre[nb] = before + x;
     }
-    const uint32_t eo = (uint32_t)skewed_len(ns);   // E's first word
-    const bool in_lds = skewed_len(ns) + skewed_len(ne) <= kSliceWords;
+    const uint32_t eo = ns;   // E's first word
+    const bool in_lds = (uint64_t)ns + ne <= kSliceWords;
     if (in_lds) {
-        for (uint32_t j = threadIdx.x; j < ns; j += blockDim.x) slice[skew(j)] = bs[s_lo + j];
-        for (uint32_t j = threadIdx.x; j < ne; j += blockDim.x) slice[eo + skew(j)] = be[e_lo + j];
+        for (uint32_t j = threadIdx.x; j < ns; j += blockDim.x) slice[j] = bs[s_lo + j];
+        for (uint32_t j = threadIdx.x; j < ne; j += blockDim.x) slice[eo + j] = be[e_lo + j];
     }
     __syncthreads();
     // per-step sums fit 32 bits when 64 counts of at most n cannot reach 2^32
