@@ -23,6 +23,8 @@
 // margin continues by galloping search in HBM.  Both only cost speed.
 #include <algorithm>
 
+#include <rocprim/warp/warp_scan.hpp>
+
 #include "bits_internal.hpp"
 
 namespace bits {
@@ -251,22 +253,20 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_place(
 // Wave-level segmented sum: lanes carry (key, value) with the keys of the
 // valid lanes non-decreasing in lane order; each run of equal keys adds its
 // sum to acc[key] with at most two LDS atomics (the run's inclusive prefix at
-// its last lane, minus the prefix before its first lane).  T = uint32_t only
-// when 64 values cannot reach 2^32.
+// its last lane, minus the prefix before its first lane, which is that lane's
+// inclusive prefix minus its own value).  The prefix sum is rocPRIM's
+// wave-wide scan, which moves data between lanes with DPP rather than through
+// the LDS.  T = uint32_t only when 64 values cannot reach 2^32.
 template <typename T>
 __device__ __forceinline__ void wave_segment_add(uint32_t key, T v, bool valid, unsigned long long* acc) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    T x = v;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const T y = __shfl_up(x, o);
-        if (lane >= (uint32_t)o) x += y;
-    }
+    T x;
+    typename rocprim::warp_scan<T, kWave>::storage_type scan_storage;
+    rocprim::warp_scan<T, kWave>().inclusive_scan(v, x, scan_storage);
     const uint32_t kp = __shfl_up(key, 1), kn = __shfl_down(key, 1);
-    const T xp = __shfl_up(x, 1);
     if (!valid) return;
     if (lane == kWave - 1 || kn != key) atomicAdd(&acc[key], (unsigned long long)x);
-    if (lane != 0 && kp != key) atomicAdd(&acc[key], 0ull - (unsigned long long)xp);
+    if (lane != 0 && kp != key) atomicAdd(&acc[key], 0ull - (unsigned long long)(x - v));
 }
 
 // The placements of one region, counted against slices S = B_S[s_lo, s_lo + ns)
@@ -310,7 +310,7 @@ __device__ __forceinline__ void bin_count_region(const uint32_t* S, uint32_t ns,
             v = (T)(first - (e_lo + rank_in<true>(E, ne, r.x)));
         }
         wave_segment_add<T>(valid ? sl : 0xFFFFFFFFu, v, valid, acc);
-        sw = __shfl(sl, kWave - 1);
+        sw = __builtin_amdgcn_readlane(sl, kWave - 1);
     }
 }
 
