@@ -5,6 +5,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -109,3 +111,37 @@ def test_host_statistics(lib):
     assert lib.bits_enrichment(5, 0, 0) == math.inf
     for obs, lo, hi in ((123456, 1000, 1003), (1, 2**40, 2**40 + 1), (10**12, 7, 8)):
         assert lib.bits_enrichment(obs, lo, hi) == oracle.enrichment(obs, lo, hi)
+
+
+def test_binned_monte_carlo_host_checks(lib):
+    """bits_mc_binned_workspace's size against the layout the header states,
+    its argument checks, and the stage timer's host side (nothing recorded yet)."""
+    from paper_1208_3407_amd import datagen
+    lens = datagen.genome_g24().astype(np.uint32)
+    cl = lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    na, n, batch = 1_000_000, 50_000_000, 1000
+    sz, mc = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    U64 = ctypes.c_uint64
+    assert lib.bits_mc_binned_workspace(U64(na), U64(n), cl, len(lens), batch, ctypes.byref(sz)) == 0
+    assert lib.bits_mc_workspace(U64(na), ctypes.byref(mc)) == 0
+    shift = 10
+    while -(-int(lens.max()) // (1 << shift)) > 8192:
+        shift += 1
+    cells = int(sum(-(-int(x) // (1 << shift)) for x in lens))
+    regions = min(cells, len(lens) + 2 * n // 8192)
+    floor_bytes = mc.value + 8 * na + 8 * batch * na + (16 + 16 * batch) * regions + 24 * cells
+    assert floor_bytes <= sz.value <= floor_bytes + 4 * cells + 64 * 1024
+    small = ctypes.c_size_t(0)
+    assert lib.bits_mc_binned_workspace(U64(na), U64(n), cl, len(lens), 256, ctypes.byref(small)) == 0
+    assert small.value < sz.value
+    for b in (0, 1025):
+        assert lib.bits_mc_binned_workspace(U64(na), U64(n), cl, len(lens), b, ctypes.byref(sz)) == 1
+    assert lib.bits_mc_binned_workspace(U64(2**32), U64(n), cl, len(lens), 8, ctypes.byref(sz)) == 1
+    big = (ctypes.c_uint32 * 2)(0xF0000000, 0xF0000000)
+    assert lib.bits_mc_binned_workspace(U64(na), U64(n), big, 2, 8, ctypes.byref(sz)) == 3
+    assert lib.bits_mc_binned(None, None, None, U64(5), cl, len(lens), U64(7), U64(0), U64(4), 8, None,
+                              ctypes.c_size_t(0), None, None, None, None, None, None) == 1
+    ms = (ctypes.c_float * 3)(1.0, 1.0, 1.0)
+    assert lib.bits_mc_binned_stage_ms(None) == 1
+    assert lib.bits_mc_binned_timing(0) == 0 and lib.bits_mc_binned_stage_ms(ms) == 0
+    assert list(ms) == [0.0, 0.0, 0.0]
