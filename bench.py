@@ -135,11 +135,19 @@ def cpu_baseline(lengths, A, B, threads):
     oracle.mc_totals(sbs, sbe, prep, MC_SEED, 0, n_shuf, threads=threads)
     t_mc = time.perf_counter() - t2
     n_evals = len(a_s) + n_shuf * N_MC
+    # the same oracle on one thread (sequential BITS), on a smaller sample: 1e6 queries + 1 shuffle
+    t3 = time.perf_counter()
+    oracle.count_sorted(sbs, sbe, a_s[:N_MC], a_e[:N_MC], threads=1)
+    oracle.mc_totals(sbs, sbe, prep, MC_SEED, 0, 1, threads=1)
+    t_one = time.perf_counter() - t3
     return {
         "value": n_evals / (t_count + t_mc),
         "unit": "A-intervals/s",
         "cores": threads,
         "kind": "oracle",
+        "value_1thread": 2 * N_MC / t_one,
+        "sample_1thread": "the same oracle on 1 thread: counts of the first %d A-intervals and 1 Monte-Carlo "
+                          "shuffle of the %d MC queries (%.2f s)" % (N_MC, N_MC, t_one),
         "sample": "oracle (C, -O2) on the same workload: projection + qsort of the full 5e7-interval B "
                   "(%.1f s, not in value), per-query counts of the first %d A-intervals on %d threads "
                   "(%.2f s) and %d Monte-Carlo shuffles of the 1e6 MC queries on %d threads (%.2f s); "
@@ -343,6 +351,12 @@ def main():
                          "totals_equal": bool(torch.equal(po["r"].totals, po["f"].totals))}
     del ref_po, po
 
+    # measured achievable HBM rate: a plain 1 GiB device copy (1 GiB read + 1 GiB written)
+    cx = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    cy = torch.empty_like(cx)
+    t_copy = timed(lambda: cy.copy_(cx), reps=5)
+    copy_gbs = 2.0 * (1 << 30) / (t_copy / 1e3) / 1e9
+    del cx, cy
     mc_avg = float(np.mean(phase["mc_ms"]))
     stage_ms = {k: float(np.mean(v)) for k, v in stages.items()}
     # dominant binned kernel of the step and its algorithmic bytes per launch (one pass of MC_BATCH
@@ -390,6 +404,7 @@ def main():
         "status": status,
         "roofline": {"bound": "hbm", "kernel": dom + " (Monte-Carlo shuffles binned by genome region)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "peak_measured_copy": copy_gbs, "frac_of_measured": achieved / copy_gbs,
                      "traffic": traffic, "bytes_per_placement_model": BYTES_PER_PLACEMENT[dom],
                      "placements_per_launch": placements, "launch_ms": dom_ms,
                      "limiter": ("LDS and VALU issue (LDS busy and bank-conflict share in "
