@@ -169,8 +169,8 @@ def main():
                     help="finish with a plain 1 GiB device copy (HBM byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (one process on one GPU); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
