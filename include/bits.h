@@ -290,7 +290,8 @@ int bits_mc_pvalue(const bits_ref *ref, const uint32_t *d_a_start, const uint32_
  * of bits_mc_workspace plus 8 bytes per query; about 24 bytes per cell of
  * the genome (cells of 2^S bp,
  * S >= 10 the least that leaves at most 8192 cells in every chromosome);
- * 16 + 16 * batch bytes per region (at most n_chrom + 2n / 8192 regions);
+ * 16 + 8 * batch * (1 + splits) bytes per region (at most n_chrom + 2n / 8192
+ * regions R; splits = min(16, ceil(2048 / R)) search workgroups per region);
  * and 8 * batch * na bytes of placement records.  BITS_E_CHROM if the
  * genome is 2^32 bp or more. */
 int bits_mc_binned_workspace(uint64_t na, uint64_t n, const uint32_t *chrom_len, uint32_t n_chrom,

@@ -472,7 +472,7 @@ bool bin_ws_layout(uint64_t na, uint64_t n, const uint32_t* chrom_len, uint32_t 
     W->desc = o; o = align256(o + (nr + 1) * 16);
     W->seg_start = o; o = align256(o + (size_t)batch * nr * sizeof(uint32_t));
     W->seg_cnt = o; o = align256(o + (size_t)batch * nr * sizeof(uint32_t));
-    W->partial = o; o = align256(o + (size_t)batch * nr * sizeof(uint64_t));
+    W->partial = o; o = align256(o + (size_t)batch * nr * W->L.splits * sizeof(uint64_t));
     W->packed = o; o = align256(o + (size_t)na * 8);
     W->recs = o; o = align256(o + (size_t)batch * na * 8);
     W->total = o;
@@ -542,6 +542,7 @@ int bits_mc_binned(const bits_ref* ref, const uint32_t* d_a_start, const uint32_
         bw.recs = w + W.recs;
         bw.packed = w + W.packed;
         bw.nreg_max = (uint32_t)W.L.nreg_max;
+        bw.splits = W.L.splits;
         BITS_CHECK_HIP(launch_mc_prepare(d_a_start, d_a_end, na, chrom_len, n_chrom, tab, ref->status, s));
         BITS_CHECK_HIP(launch_mc(make_search_args(ref, cfg), cfg, d_a_start, d_a_end, tab, na, seed, s0, 0, totals,
                                  obs, s));

@@ -37,6 +37,11 @@ constexpr uint32_t kRegionKeys = 8192;     // merged B_S + B_E keys per region (
 constexpr uint32_t kMargin = 256;          // B_S keys staged past a region's end
 constexpr uint32_t kSliceWords = 14336;    // LDS slice capacity of the search kernel (56 KiB)
 constexpr uint32_t kBinThreads = 1024;
+// A reference with few regions (a small B) would leave most of the chip idle
+// in the search; each region's records are then split over up to kMaxSplits
+// workgroups, aiming at kSearchWorkgroups per pass.
+constexpr uint32_t kSearchWorkgroups = 2048;
+constexpr uint32_t kMaxSplits = 16;
 
 // Per-chromosome geometry, passed by value: off[k] = first coordinate of
 // chromosome k (off[n] = genome size), cb[k] = its first cell (cb[n] = cells).
@@ -270,20 +275,20 @@ __device__ __forceinline__ void wave_segment_add(uint32_t key, T v, bool valid, 
 }
 
 // The placements of one region, counted against slices S = B_S[s_lo, s_lo + ns)
-// and E = B_E[e_lo, e_lo + ne) (in LDS, or in HBM for an oversize region).  Each wave takes a contiguous range of the region's
-// records, 64 per step; records are grouped by shuffle (pre[s] = first
-// record of shuffle s), so a wave tracks its shuffle by a forward scan and
-// adds per-shuffle sums with wave_segment_add.
+// and E = B_E[e_lo, e_lo + ne) (in LDS, or in HBM for an oversize region):
+// the workgroup's share [q0, q1) of the region's records.  Each wave takes a
+// contiguous range of it, 64 records per step; records are grouped by
+// shuffle (pre[s] = first record of shuffle s), so a wave tracks its shuffle
+// by a forward scan and adds per-shuffle sums with wave_segment_add.
 template <bool LDS, typename T>
 __device__ __forceinline__ void bin_count_region(const uint32_t* S, uint32_t ns, const uint32_t* E, uint32_t ne,
                                                  const uint32_t* __restrict__ bs, uint32_t n, uint32_t s_lo,
                                                  uint32_t e_lo, const uint2* __restrict__ recs, uint64_t na,
                                                  const uint64_t* pre, const uint32_t* sst, uint32_t nb,
-                                                 unsigned long long* acc) {
+                                                 uint64_t q0, uint64_t q1, unsigned long long* acc) {
     const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    const uint64_t total = pre[nb];
-    const uint64_t steps = (total + kWave - 1) / kWave, per = (steps + nw - 1) / nw;
-    const uint64_t p0 = (uint64_t)wv * per * kWave, p1 = min(total, p0 + per * kWave);
+    const uint64_t steps = (q1 - q0 + kWave - 1) / kWave, per = (steps + nw - 1) / nw;
+    const uint64_t p0 = q0 + (uint64_t)wv * per * kWave, p1 = min(q1, p0 + per * kWave);
     if (p0 >= p1) return;
     const uint32_t s_end = s_lo + ns;
     // shuffle of the wave's first record: the last s with pre[s] <= p0
@@ -314,20 +319,22 @@ __device__ __forceinline__ void bin_count_region(const uint32_t* S, uint32_t ns,
     }
 }
 
-// One workgroup per region r < nreg (nreg on the device; workgroups past it
-// return): stage the slices, count every placement of the batch that starts
-// in the region, write partial[r * nb + s].
+// `splits` workgroups per region r < nreg (nreg on the device; workgroups past
+// it return): stage the slices, count the workgroup's share of the placements
+// of the batch that start in the region, write partial[(r * splits + part) * nb + s].
+// SPLIT = false is the one-workgroup-per-region form (splits = 1).
+template <bool SPLIT>
 __global__ void __launch_bounds__(kBinThreads) k_bin_search(
     const uint32_t* __restrict__ bs, const uint32_t* __restrict__ be, uint32_t n,
     const RegionDesc* __restrict__ desc, const uint64_t* __restrict__ nreg_p, const uint32_t* __restrict__ seg_start,
     const uint32_t* __restrict__ seg_cnt, uint32_t nreg_max, uint32_t nb, const uint2* __restrict__ recs,
-    uint64_t na, unsigned long long* __restrict__ partial) {
+    uint64_t na, uint32_t splits, unsigned long long* __restrict__ partial) {
     __shared__ uint32_t slice[kSliceWords];
     __shared__ uint64_t pre[BITS_MC_BIN_MAX_BATCH + 1];
     __shared__ uint32_t sst[BITS_MC_BIN_MAX_BATCH];
     __shared__ unsigned long long acc[BITS_MC_BIN_MAX_BATCH];
     __shared__ uint64_t w64[kBinThreads / kWave];
-    const uint32_t r = blockIdx.x;
+    const uint32_t r = SPLIT ? blockIdx.x / splits : blockIdx.x, part = SPLIT ? blockIdx.x - r * splits : 0u;
     if (r >= *nreg_p) return;
     const RegionDesc d0 = desc[r], d1 = desc[r + 1];
     const uint32_t s_lo = d0.s_lo, e_lo = d0.e_lo;
@@ -362,32 +369,38 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_search(
         for (uint32_t j = threadIdx.x; j < ne; j += blockDim.x) slice[eo + j] = be[e_lo + j];
     }
     __syncthreads();
+    // this workgroup's share of the region's records
+    const uint64_t total = pre[nb];
+    const uint64_t q0 = SPLIT ? total * part / splits : 0ull, q1 = SPLIT ? total * (part + 1) / splits : total;
     // per-step sums fit 32 bits when 64 counts of at most n cannot reach 2^32
     const bool narrow = n < (1u << 26);
     if (in_lds && narrow)
-        bin_count_region<true, uint32_t>(slice, ns, slice + eo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb, acc);
+        bin_count_region<true, uint32_t>(slice, ns, slice + eo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb, q0,
+                                         q1, acc);
     else if (in_lds)
-        bin_count_region<true, uint64_t>(slice, ns, slice + eo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb, acc);
+        bin_count_region<true, uint64_t>(slice, ns, slice + eo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb, q0,
+                                         q1, acc);
     else if (narrow)
         bin_count_region<false, uint32_t>(bs + s_lo, ns, be + e_lo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb,
-                                          acc);
+                                          q0, q1, acc);
     else
         bin_count_region<false, uint64_t>(bs + s_lo, ns, be + e_lo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb,
-                                          acc);
+                                          q0, q1, acc);
     __syncthreads();
-    if (threadIdx.x < nb) partial[(uint64_t)r * nb + threadIdx.x] = acc[threadIdx.x];
+    if (threadIdx.x < nb)
+        partial[(SPLIT ? (uint64_t)r * splits + part : (uint64_t)r) * nb + threadIdx.x] = acc[threadIdx.x];
 }
 
-// totals[s] += sum over regions r < nreg of partial[r * nb + s]; blockIdx.y
-// takes every gridDim.y-th region.
+// totals[s] += sum over the nreg * splits region shares j of partial[j * nb + s];
+// blockIdx.y takes every gridDim.y-th share.
 __global__ void __launch_bounds__(256) k_bin_reduce(const unsigned long long* __restrict__ partial,
-                                                    const uint64_t* __restrict__ nreg_p, uint32_t nb,
-                                                    unsigned long long* __restrict__ totals) {
+                                                    const uint64_t* __restrict__ nreg_p, uint32_t splits,
+                                                    uint32_t nb, unsigned long long* __restrict__ totals) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nb) return;
-    const uint64_t nreg = *nreg_p;
+    const uint64_t shares = *nreg_p * splits;
     unsigned long long v = 0ull;
-    for (uint64_t r = blockIdx.y; r < nreg; r += gridDim.y) v += partial[r * nb + s];
+    for (uint64_t j = blockIdx.y; j < shares; j += gridDim.y) v += partial[j * nb + s];
     if (v) atomicAdd(totals + s, v);
 }
 
@@ -426,6 +439,8 @@ bool bin_layout(const uint32_t* chrom_len, uint32_t n_chrom, uint64_t n, BinLayo
     for (uint32_t k = 0; k < n_chrom; ++k) with_cells += g.cb[k + 1] > g.cb[k];
     const uint64_t bound = with_cells + (2 * n) / kRegionKeys;
     L->nreg_max = L->ncells < bound ? L->ncells : bound;
+    const uint64_t sp = L->nreg_max ? (kSearchWorkgroups + L->nreg_max - 1) / L->nreg_max : 1;
+    L->splits = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(sp, 1), kMaxSplits);
     return true;
 }
 
@@ -467,13 +482,18 @@ hipError_t launch_bin_batch(const uint32_t* chrom_len, uint32_t n_chrom, const M
                        reinterpret_cast<const uint2*>(w.packed), tab.hist, tab.cursor, na, seed, sb, nb,
                        w.cell_region, w.offsets, w.nreg_max, w.seg_start, w.seg_cnt, reinterpret_cast<uint2*>(w.recs));
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bin_search, dim3(w.nreg_max), dim3(kBinThreads), 0, s, bs, be, n,
-                       reinterpret_cast<const RegionDesc*>(w.desc), w.offsets + ncells, w.seg_start, w.seg_cnt,
-                       w.nreg_max, nb, reinterpret_cast<const uint2*>(w.recs), na, w.partial);
+    if (w.splits > 1)
+        hipLaunchKernelGGL(k_bin_search<true>, dim3(w.nreg_max * w.splits), dim3(kBinThreads), 0, s, bs, be, n,
+                           reinterpret_cast<const RegionDesc*>(w.desc), w.offsets + ncells, w.seg_start, w.seg_cnt,
+                           w.nreg_max, nb, reinterpret_cast<const uint2*>(w.recs), na, w.splits, w.partial);
+    else
+        hipLaunchKernelGGL(k_bin_search<false>, dim3(w.nreg_max), dim3(kBinThreads), 0, s, bs, be, n,
+                           reinterpret_cast<const RegionDesc*>(w.desc), w.offsets + ncells, w.seg_start, w.seg_cnt,
+                           w.nreg_max, nb, reinterpret_cast<const uint2*>(w.recs), na, 1u, w.partial);
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
-    const uint32_t gy = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(w.nreg_max / 64, 1), 256);
-    hipLaunchKernelGGL(k_bin_reduce, dim3((nb + 255) / 256, gy), dim3(256), 0, s, w.partial, w.offsets + ncells, nb,
-                       totals);
+    const uint32_t gy = (uint32_t)std::min<uint64_t>(std::max<uint64_t>((uint64_t)w.nreg_max * w.splits / 64, 1), 256);
+    hipLaunchKernelGGL(k_bin_reduce, dim3((nb + 255) / 256, gy), dim3(256), 0, s, w.partial, w.offsets + ncells,
+                       w.splits, nb, totals);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return e;
     return hipSuccess;

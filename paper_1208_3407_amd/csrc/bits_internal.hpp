@@ -209,6 +209,7 @@ hipError_t launch_count_rounds(const uint32_t* S, const uint32_t* E, uint64_t nb
 // binned.hip: the Monte-Carlo path binned by genome region.
 struct BinLayout {
     uint64_t ncells, nreg_max;
+    uint32_t splits;              // search workgroups per region
 };
 // Cell count and an upper bound on the region count for a genome and |B| = n;
 // false if the genome cannot be cut (sizes past 2^32).
@@ -220,10 +221,10 @@ struct BinWs {                    // device buffers, carved from the caller's wo
     uint32_t* cell_region;        // [ncells]
     void* desc;                   // [nreg_max + 1] region descriptors (16 bytes)
     uint32_t *seg_start, *seg_cnt;    // [batch][nreg_max]
-    unsigned long long* partial;      // [nreg_max][batch]
+    unsigned long long* partial;      // [nreg_max * splits][batch]
     void* recs;                       // [batch][na] {start, end}
     void* packed;                     // [na] {input index, length or 0}
-    uint32_t nreg_max;
+    uint32_t nreg_max, splits;
 };
 hipError_t launch_bin_pack(const McTable& tab, uint64_t na, const BinWs& w, hipStream_t s);
 hipError_t launch_bin_regions(const uint32_t* chrom_len, uint32_t n_chrom, const uint32_t* bs, const uint32_t* be,
