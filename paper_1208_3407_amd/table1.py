@@ -7,7 +7,10 @@ the 24-chromosome genome, log-normal lengths with median 200 bp) and 1, 100,
           database set B, sorts it again and counts A against it;
   fixed   this library's loop (bits_mc_pvalue): the reference is built once
           from A (sort, line heads, learned index) and every round randomises
-          B and searches it in A's index; the per-round totals are the same.
+          B and searches it in A's index; the per-round totals are the same;
+  binned  the same loop binned by genome region (bits_mc_binned): the
+          placements of a batch of rounds are grouped by region of A's
+          reference and counted in LDS; the per-round totals are the same.
 
 A cell is setup (projection and sorting / index build) plus the rounds.
 Rounds beyond a cap are timed on the cap and scaled linearly; such cells are
@@ -59,12 +62,15 @@ def one_size(n, cap, seed=1):
     batch = int(max(1, min(64, (1 << 26) // n)))
     ws_r = bits._scratch(bits.bits_mc_resort_workspace(n, batch), dev)
     ws_f = bits._scratch(bits.bits_mc_workspace(n), dev)
+    bb = int(max(1, min(1000, (1 << 29) // n)))        # binned rounds per pass: records stay under 4 GiB
+    ws_b = bits._scratch(bits.bits_mc_binned_workspace(n, n, lengths, bb), dev)
     # warm-up (loads kernels, sizes the caches)
     a_s, a_e = bits.bits_project(lengths, *dA)
     b_s, b_e = bits.bits_project(lengths, *dB)
     bits.bits_mc_resort(a_s, a_e, b_s, b_e, lengths, 7, 0, 2, batch=batch, workspace=ws_r)
     ref = bits.bits_sort_ref(a_s, a_e, learned=True)
     bits.bits_mc_pvalue(ref, b_s, b_e, lengths, 7, 0, 2, workspace=ws_f)
+    bits.bits_mc_binned(ref, b_s, b_e, lengths, 7, 0, 2, batch=bb, workspace=ws_b)
     torch.cuda.synchronize()
 
     # setup: projection (+ the index build of the fixed orientation)
@@ -75,15 +81,18 @@ def one_size(n, cap, seed=1):
     t_resort, mr = gpu_ms(lambda: bits.bits_mc_resort(a_s, a_e, b_s, b_e, lengths, 7, 0, rounds_timed, batch=batch,
                                                       workspace=ws_r))
     t_fixed, mf = gpu_ms(lambda: bits.bits_mc_pvalue(ref, b_s, b_e, lengths, 7, 0, rounds_timed, workspace=ws_f))
-    same = bool(torch.equal(mr.totals, mf.totals))
-    per_r, per_f = t_resort / rounds_timed, t_fixed / rounds_timed
-    row = {"size": n, "batch": batch, "rounds_timed": rounds_timed, "totals_equal": same,
+    t_binned, mb = gpu_ms(lambda: bits.bits_mc_binned(ref, b_s, b_e, lengths, 7, 0, rounds_timed, batch=bb,
+                                                      workspace=ws_b))
+    same = bool(torch.equal(mr.totals, mf.totals)) and bool(torch.equal(mb.totals, mf.totals))
+    per_r, per_f, per_b = t_resort / rounds_timed, t_fixed / rounds_timed, t_binned / rounds_timed
+    row = {"size": n, "batch": batch, "binned_batch": bb, "rounds_timed": rounds_timed, "totals_equal": same,
            "setup_ms": {"projection": t_proj, "index": t_index},
-           "per_round_ms": {"resort": per_r, "fixed": per_f}, "cells_s": {}}
+           "per_round_ms": {"resort": per_r, "fixed": per_f, "binned": per_b}, "cells_s": {}}
     for r in ROUNDS:
         row["cells_s"][str(r)] = {
             "resort": (t_proj + r * per_r) / 1e3,
             "fixed": (t_proj + t_index + r * per_f) / 1e3,
+            "binned": (t_proj + t_index + r * per_b) / 1e3,
             "extrapolated": r > rounds_timed}
     return row
 
@@ -103,7 +112,7 @@ def main():
     print("| Size | Orientation | " + " | ".join("%d rounds" % r for r in ROUNDS) + " |")
     print("|---|---|" + "---|" * len(ROUNDS))
     for row in rows:
-        for o, name in (("resort", "resort (paper's loop)"), ("fixed", "fixed index")):
+        for o, name in (("resort", "resort (paper's loop)"), ("fixed", "fixed index"), ("binned", "fixed index, binned")):
             cells = []
             for r in ROUNDS:
                 c = row["cells_s"][str(r)]
