@@ -13,11 +13,13 @@
 //            queries are made (the Philox stream of the other Monte-Carlo
 //            kernels), counted per region, made again and written, with their
 //            ends, in region order: one segment per (shuffle, region);
-//   search   per region: both slices are staged in LDS (B_S with kMargin keys
+//   search   per region (or per share of a region's records when regions
+//            are few): both slices are staged in LDS (B_S with kMargin keys
 //            past the region's end, for ends that cross it), each placement of
 //            each shuffle of the batch is counted by two bisections in LDS, and
 //            the per-shuffle sums are written out;
-//   reduce   per shuffle: the sums over regions are added to the totals.
+//   reduce   per shuffle: the sums over regions (and shares) are added to the
+//            totals.
 // A region whose slices exceed the LDS capacity (very dense or duplicated
 // keys) is searched in HBM by the same bisections; an end past the staged
 // margin continues by galloping search in HBM.  Both only cost speed.
