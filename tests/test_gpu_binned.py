@@ -146,3 +146,25 @@ def test_binned_at_monte_carlo_scale():
     a_s, a_e = oracle.project(lengths, A.chrom, A.start, A.end)
     b_s, b_e = oracle.project(lengths, B.chrom, B.start, B.end)
     check(lengths, a_s, a_e, b_s, b_e, 7, 0, 40, 16, learned=True)
+
+
+def test_binned_stage_timer():
+    """The stage timer records one set of events per pass while on (positive times, the
+    binning and search kernels of every pass summed) and nothing while off; the totals
+    are the same either way."""
+    note("case: binned stage timer")
+    lengths, A, B = datagen.w2_sets(seed=5, n_a=2000, n_b=50_000)
+    a_s, a_e = oracle.project(lengths, A.chrom, A.start, A.end)
+    b_s, b_e = oracle.project(lengths, B.chrom, B.start, B.end)
+    ref = bits.bits_sort_ref(up(b_s), up(b_e))
+    plain = bits.bits_mc_binned(ref, up(a_s), up(a_e), lengths, 7, 0, 10, batch=4)
+    bits.bits_mc_binned_timing(True)
+    try:
+        timed = bits.bits_mc_binned(ref, up(a_s), up(a_e), lengths, 7, 0, 10, batch=4)   # three passes
+        st = bits.bits_mc_binned_stage_ms()
+    finally:
+        bits.bits_mc_binned_timing(False)
+    assert st["place"] > 0.0 and st["search"] > 0.0 and st["reduce"] > 0.0
+    assert np.array_equal(down(timed.totals), down(plain.totals))
+    bits.bits_mc_binned(ref, up(a_s), up(a_e), lengths, 7, 0, 10, batch=4)
+    assert bits.bits_mc_binned_stage_ms() == {"place": 0.0, "search": 0.0, "reduce": 0.0}
