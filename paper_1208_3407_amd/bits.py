@@ -17,8 +17,7 @@ from typing import List, Optional, Sequence, Tuple
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# BITS_LIBRARY may name another build of the same library (e.g. a tuning variant)
-LIB_PATH = os.environ.get("BITS_LIBRARY") or os.path.join(_HERE, "libbits.so")
+LIB_PATH = os.path.join(_HERE, "libbits.so")
 
 BITS_OK = 0
 BITS_FLAG_INTERVAL = 0x1
@@ -391,11 +390,30 @@ class MCResult:
     n_le: torch.Tensor       # uint64[1]
 
 
+def _check_mc_args(a_start: torch.Tensor, a_end: torch.Tensor, s0: int, s1: int, out: Optional["MCResult"]):
+    """Host-side checks shared by the Monte-Carlo wrappers: equal query array
+    lengths, a shuffle range with s0 <= s1, and caller-supplied outputs large
+    enough for the kernels to write (uint64, contiguous, totals >= s1 - s0)."""
+    if a_end.numel() != a_start.numel():
+        raise BitsError("a_start and a_end differ in length")
+    if int(s1) < int(s0):
+        raise BitsError("shuffle range [s0, s1) has s1 < s0")
+    if out is None:
+        return
+    for name, t, need in (("totals", out.totals, int(s1) - int(s0)), ("observed", out.observed, 1),
+                          ("n_ge", out.n_ge, 1), ("n_le", out.n_le, 1)):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.uint64 or not t.is_contiguous():
+            raise BitsError("out.%s must be a contiguous uint64 tensor" % name)
+        if t.numel() < need:
+            raise BitsError("out.%s holds %d values, needs %d" % (name, t.numel(), need))
+
+
 def bits_mc_pvalue(ref: Ref, a_start, a_end, chrom_len, seed: int, s0: int, s1: int, launch=None,
                    workspace: Optional[torch.Tensor] = None, out: Optional[MCResult] = None, stream=None) -> MCResult:
     """Monte-Carlo shuffles [s0, s1) of A against the reference, in one persistent launch."""
     dev = _device()
     a_start, a_end = _u32_dev(a_start, "a_start"), _u32_dev(a_end, "a_end")
+    _check_mc_args(a_start, a_end, s0, s1, out)
     na = a_start.numel()
     if workspace is None:
         workspace = _scratch(bits_mc_workspace(na), dev)
@@ -427,6 +445,7 @@ def bits_mc_binned(ref: Ref, a_start, a_end, chrom_len, seed: int, s0: int, s1: 
     counted in LDS, `batch` shuffles per pass; same totals as bits_mc_pvalue."""
     dev = _device()
     a_start, a_end = _u32_dev(a_start, "a_start"), _u32_dev(a_end, "a_end")
+    _check_mc_args(a_start, a_end, s0, s1, out)
     na = a_start.numel()
     if workspace is None:
         workspace = _scratch(bits_mc_binned_workspace(na, ref.n, chrom_len, batch), dev)

@@ -25,8 +25,6 @@
 // margin continues by galloping search in HBM.  Both only cost speed.
 #include <algorithm>
 
-#include <rocprim/warp/warp_scan.hpp>
-
 #include "bits_internal.hpp"
 
 namespace bits {
@@ -257,20 +255,53 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_place(
     }
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave, moving data between lanes
+// with DPP only (no LDS instruction, so it does not queue behind the
+// bisections): four row_shr steps (1, 2, 4, 8) build the prefix inside each
+// row of 16 lanes, then row_bcast:15 adds row 0's total to row 1 and row 2's
+// to row 3, and row_bcast:31 adds the total of rows 0-1 to rows 2 and 3.
+// Lanes whose source lies outside the row, and rows the row mask leaves out,
+// receive 0 (the `old` operand), so every step is a plain add.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_in0(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void scan_step(uint32_t& x) {
+    x += dpp_in0<CTRL, ROWS>(x);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void scan_step(uint64_t& x) {
+    const uint32_t lo = dpp_in0<CTRL, ROWS>((uint32_t)x), hi = dpp_in0<CTRL, ROWS>((uint32_t)(x >> 32));
+    x += ((uint64_t)hi << 32) | lo;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T x) {
+    scan_step<0x111, 0xF>(x);   // row_shr:1
+    scan_step<0x112, 0xF>(x);   // row_shr:2
+    scan_step<0x114, 0xF>(x);   // row_shr:4
+    scan_step<0x118, 0xF>(x);   // row_shr:8
+    scan_step<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
+    scan_step<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
 // Wave-level segmented sum: lanes carry (key, value) with the keys of the
 // valid lanes non-decreasing in lane order; each run of equal keys adds its
 // sum to acc[key] with at most two LDS atomics (the run's inclusive prefix at
 // its last lane, minus the prefix before its first lane, which is that lane's
-// inclusive prefix minus its own value).  The prefix sum is rocPRIM's
-// wave-wide scan, which moves data between lanes with DPP rather than through
-// the LDS.  T = uint32_t only when 64 values cannot reach 2^32.
+// inclusive prefix minus its own value).  T = uint32_t only when 64 values
+// cannot reach 2^32.
 template <typename T>
 __device__ __forceinline__ void wave_segment_add(uint32_t key, T v, bool valid, unsigned long long* acc) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    T x;
-    typename rocprim::warp_scan<T, kWave>::storage_type scan_storage;
-    rocprim::warp_scan<T, kWave>().inclusive_scan(v, x, scan_storage);
-    const uint32_t kp = __shfl_up(key, 1), kn = __shfl_down(key, 1);
+    const T x = wave_inclusive_scan<T>(v);
+    // the neighbours' keys by whole-wave DPP shifts (wave_shr:1, wave_shl:1); lane 0's kp and
+    // lane 63's kn are never used
+    const uint32_t kp = dpp_in0<0x138, 0xF>(key), kn = dpp_in0<0x130, 0xF>(key);
     if (!valid) return;
     if (lane == kWave - 1 || kn != key) atomicAdd(&acc[key], (unsigned long long)x);
     if (lane != 0 && kp != key) atomicAdd(&acc[key], 0ull - (unsigned long long)(x - v));

@@ -145,3 +145,28 @@ def test_binned_monte_carlo_host_checks(lib):
     assert lib.bits_mc_binned_stage_ms(None) == 1
     assert lib.bits_mc_binned_timing(0) == 0 and lib.bits_mc_binned_stage_ms(ms) == 0
     assert list(ms) == [0.0, 0.0, 0.0]
+
+
+def test_monte_carlo_wrappers_refuse_mismatched_buffers():
+    """The binding's Monte-Carlo wrappers refuse query arrays of different
+    lengths, an inverted shuffle range and output buffers the kernels would
+    overrun, before any call into the library."""
+    import torch
+    from paper_1208_3407_amd import bits
+    a = torch.zeros(10, dtype=torch.uint32)
+    u64 = lambda n: torch.zeros(n, dtype=torch.uint64)   # noqa: E731
+    ok = bits.MCResult(u64(8), u64(1), u64(1), u64(1))
+    bits._check_mc_args(a, a, 2, 10, ok)
+    bits._check_mc_args(a, a, 5, 5, None)
+    with pytest.raises(bits.BitsError, match="differ in length"):
+        bits._check_mc_args(a, a[:9], 0, 8, ok)
+    with pytest.raises(bits.BitsError, match="s1 < s0"):
+        bits._check_mc_args(a, a, 9, 8, None)
+    with pytest.raises(bits.BitsError, match="totals holds 7"):
+        bits._check_mc_args(a, a, 0, 8, bits.MCResult(u64(7), u64(1), u64(1), u64(1)))
+    with pytest.raises(bits.BitsError, match="n_le holds 0"):
+        bits._check_mc_args(a, a, 0, 8, bits.MCResult(u64(8), u64(1), u64(1), u64(0)))
+    with pytest.raises(bits.BitsError, match="uint64"):
+        bits._check_mc_args(a, a, 0, 8, bits.MCResult(torch.zeros(8, dtype=torch.int32), u64(1), u64(1), u64(1)))
+    with pytest.raises(bits.BitsError, match="uint64"):
+        bits._check_mc_args(a, a, 0, 4, bits.MCResult(u64(16)[::2], u64(1), u64(1), u64(1)))

@@ -1,9 +1,13 @@
-"""GPU parity at the workloads' full sizes, in the launch shapes bench.py
-times.  The oracle recomputes sampled outputs one by one (per-query counts of
-sampled queries, sampled shuffles, sampled pairs); totals are checked against
-the oracle's independent endpoint merge; the rest through properties that
-hold at any size (learned == plain, tail counts from the totals)."""
+"""GPU parity at the workloads' full sizes, against the oracle on every output:
+all per-query counts (1e7 and 5e7 queries), every shuffle total of the two
+Monte-Carlo workloads (10,000 x 1e5 and 1,000 x 1e6), the observed totals and
+the tail counts and p-values recomputed from the oracle's own totals, and all
+2,048 pair totals of the uneven batch.  Every launch shape the autotuner can
+pick for the counting kernels is run at full size, so whichever shape
+bench.py times is covered.  The oracle runs multithreaded (about 2e9
+evaluations in all)."""
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -18,7 +22,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 from paper_1208_3407_amd import bits  # noqa: E402
 
-from bench import RECORDED_LEARNED, RECORDED_MC, RECORDED_PLAIN  # noqa: E402  (bench's launch shapes)
+from bench import MC_BATCH  # noqa: E402  (bench's binned pass size)
 
 DEV = torch.device("cuda", 0)
 THREADS = 16
@@ -43,54 +47,92 @@ def proj(lengths, S):
     return gs, ge
 
 
-def test_w1_full_per_query_sampled_and_total():
-    note("case: W1 full 1e7 x 1e7")
+def count_shapes(ref, path):
+    """Every launch shape bits_autotune_count tries for this reference and path."""
+    out = []
+    dmin = min(ref.depth, 8)
+    for block in (256, 512, 1024):
+        for qpl in (1, 2, 4):
+            if path == bits.BITS_PATH_LEARNED:
+                out.append({"block": block, "qpl": qpl, "depth": 0, "grid": 0, "path": path})
+            else:
+                for d in range(ref.depth, dmin - 1, -1):
+                    out.append({"block": block, "qpl": qpl, "depth": d, "grid": 0, "path": path})
+    return out
+
+
+def check_all_shapes(ref, a_s, a_e, exp_dev, total):
+    """Per-query counts equal the oracle's (compared on the device) and the
+    total equals it, at every candidate shape of both search paths."""
+    counts = torch.empty_like(exp_dev)
+    tot = torch.empty(1, dtype=torch.uint64, device=DEV)
+    n = 0
+    for path in (bits.BITS_PATH_LEARNED, bits.BITS_PATH_PLAIN):
+        for lp in count_shapes(ref, path):
+            bits.bits_count_per_query(ref, a_s, a_e, launch=lp, counts=counts, total=tot)
+            assert torch.equal(counts, exp_dev), lp
+            assert int(down(tot)[0]) == total, lp
+            n += 1
+    return n
+
+
+def oracle_sets(lengths, S):
+    return oracle.project(lengths, S.chrom, S.start, S.end)
+
+
+def check_mc(mc, exp_T, obs, N):
+    """Totals, observed, tail counts and p-value against the oracle's own totals."""
+    assert np.array_equal(down(mc.totals), exp_T)
+    assert int(down(mc.observed)[0]) == obs
+    ge, le = oracle.mc_tail(exp_T, obs)
+    assert (int(down(mc.n_ge)[0]), int(down(mc.n_le)[0])) == (ge, le)
+    assert bits.bits_pvalue(int(down(mc.n_ge)[0]), N) == oracle.pvalue(ge, N)
+
+
+def test_w1_full_every_count():
+    note("case: W1 full 1e7 x 1e7, every per-query count, every launch shape")
     lengths, A, B = datagen.w1_sets()
     a_s, a_e = proj(lengths, A)
     b_s, b_e = proj(lengths, B)
     ref = bits.bits_sort_ref(b_s, b_e, learned=True)
-    c_plain, t_plain = bits.bits_count_per_query(ref, a_s, a_e, launch=RECORDED_PLAIN)
-    c_plain = down(c_plain).copy()
-    c_learn, t_learn = bits.bits_count_per_query(ref, a_s, a_e, launch=RECORDED_LEARNED)
-    assert np.array_equal(down(c_learn), c_plain)
-    oa_s, oa_e = oracle.project(lengths, A.chrom, A.start, A.end)
-    ob_s, ob_e = oracle.project(lengths, B.chrom, B.start, B.end)
+    oa_s, oa_e = oracle_sets(lengths, A)
+    ob_s, ob_e = oracle_sets(lengths, B)
+    t0 = time.time()
     sbs, sbe = oracle.sort_u32(ob_s), oracle.sort_u32(ob_e)
-    idx = np.unique(np.concatenate([np.arange(1000), np.random.default_rng(0).integers(0, len(oa_s), 100_000),
-                                    np.arange(len(oa_s) - 1000, len(oa_s))]))
-    exp, _ = oracle.count_sorted(sbs, sbe, oa_s[idx], oa_e[idx], threads=THREADS)
-    assert np.array_equal(c_plain[idx], exp)
-    total = oracle.sweep_total(oa_s, oa_e, ob_s, ob_e)
-    assert int(down(t_plain)[0]) == total and int(down(t_learn)[0]) == total
-    assert int(c_plain.astype(np.uint64).sum()) == total
+    exp, total = oracle.count_sorted(sbs, sbe, oa_s, oa_e, threads=THREADS)
+    assert total == oracle.sweep_total(oa_s, oa_e, ob_s, ob_e)
+    note("  oracle %.1f s" % (time.time() - t0))
+    assert np.array_equal(down(ref.sorted_starts()), sbs) and np.array_equal(down(ref.sorted_ends()), sbe)
+    n = check_all_shapes(ref, a_s, a_e, up(exp), total)
+    note("  %d launch shapes equal the oracle on all 1e7 counts" % n)
     assert bits.bits_get_status(ref) == 0
 
 
-def test_w2_full_monte_carlo_sampled_shuffles():
-    note("case: W2 full, 10,000 shuffles")
+def test_w2_full_monte_carlo_every_shuffle():
+    note("case: W2 full, all 10,000 shuffles vs the oracle")
     lengths, A, B = datagen.w2_sets()
     a_s, a_e = proj(lengths, A)
     b_s, b_e = proj(lengths, B)
     ref = bits.bits_sort_ref(b_s, b_e, learned=True)
     N = 10_000
-    mc = bits.bits_mc_pvalue(ref, a_s, a_e, lengths, datagen.MC_SEED, 0, N, launch=RECORDED_MC)
-    T = down(mc.totals).copy()
-    obs, ge, le = int(down(mc.observed)[0]), int(down(mc.n_ge)[0]), int(down(mc.n_le)[0])
-    mcp = bits.bits_mc_pvalue(ref, a_s, a_e, lengths, datagen.MC_SEED, 0, N, launch=RECORDED_PLAIN)
-    assert np.array_equal(down(mcp.totals), T)
-    oa_s, oa_e = oracle.project(lengths, A.chrom, A.start, A.end)
-    ob_s, ob_e = oracle.project(lengths, B.chrom, B.start, B.end)
+    oa_s, oa_e = oracle_sets(lengths, A)
+    ob_s, ob_e = oracle_sets(lengths, B)
     sbs, sbe = oracle.sort_u32(ob_s), oracle.sort_u32(ob_e)
     prep = oracle.mc_prepare(lengths, oa_s, oa_e)
-    for s in (0, 1, 2, 4999, 9998, 9999):
-        assert int(T[s]) == int(oracle.mc_totals(sbs, sbe, prep, datagen.MC_SEED, s, s + 1)[0]), s
-    assert obs == oracle.count_sorted(sbs, sbe, oa_s, oa_e, threads=THREADS, per_query=False)[1]
-    assert (ge, le) == oracle.mc_tail(T, obs)
-    assert bits.bits_pvalue(ge, N) == oracle.pvalue(ge, N)
+    t0 = time.time()
+    exp_T = oracle.mc_totals(sbs, sbe, prep, datagen.MC_SEED, 0, N, threads=THREADS)
+    obs = oracle.count_sorted(sbs, sbe, oa_s, oa_e, threads=THREADS, per_query=False)[1]
+    note("  oracle %.1f s for 1e9 evaluations" % (time.time() - t0))
+    for lp in ({"block": 1024, "qpl": 1, "depth": 0, "grid": 0, "path": 2},
+               {"block": 512, "qpl": 1, "depth": 0, "grid": 0, "path": 2},
+               {"block": 256, "qpl": 1, "depth": 13, "grid": 0, "path": 1}):
+        check_mc(bits.bits_mc_pvalue(ref, a_s, a_e, lengths, datagen.MC_SEED, 0, N, launch=lp), exp_T, obs, N)
+    check_mc(bits.bits_mc_binned(ref, a_s, a_e, lengths, datagen.MC_SEED, 0, N, batch=MC_BATCH), exp_T, obs, N)
+    assert bits.bits_get_status(ref) == 0
 
 
-def test_w3_full_batch_sampled_pairs():
-    note("case: W3 full 32 x 64 pairs")
+def test_w3_full_batch_every_pair():
+    note("case: W3 full 32 x 64 pairs, all 2,048 totals vs the oracle")
     lengths, Q, R = datagen.w3_sets()
     qd = [proj(lengths, S) for S in Q]
     rd = [proj(lengths, S) for S in R]
@@ -99,82 +141,102 @@ def test_w3_full_batch_sampled_pairs():
     got1 = down(bits.bits_batch_run(plan)).copy()
     got2 = down(bits.bits_batch_run(plan)).reshape(len(Q), len(R))
     assert np.array_equal(got1.reshape(len(Q), len(R)), got2)
-    qsz = np.array([len(S) for S in Q])
-    rsz = np.array([len(S) for S in R])
-    pairs = {(int(np.argmax(qsz)), int(np.argmax(rsz))), (int(np.argmin(qsz)), int(np.argmin(rsz))),
-             (int(np.argmax(qsz)), int(np.argmin(rsz))), (3, 17), (31, 63), (0, 0)}
-    for i, j in sorted(pairs):
-        qs, qe = oracle.project(lengths, Q[i].chrom, Q[i].start, Q[i].end)
-        rs, re_ = oracle.project(lengths, R[j].chrom, R[j].start, R[j].end)
+    t0 = time.time()
+    oq = [oracle_sets(lengths, S) for S in Q]
+    exp = np.zeros((len(Q), len(R)), np.uint64)
+    for j, S in enumerate(R):
+        rs, re_ = oracle_sets(lengths, S)
         sbs, sbe = oracle.sort_u32(rs), oracle.sort_u32(re_)
-        exp = oracle.count_sorted(sbs, sbe, qs, qe, threads=THREADS, per_query=False)[1]
-        assert int(got2[i, j]) == exp, (i, j)
-    # every pair equals the single-pair entry point on the same reference
-    for i in (0, 5, 31):
-        for j in (0, 40, 63):
-            assert int(down(bits.bits_count(refs[j], qd[i][0], qd[i][1]))[0]) == int(got2[i, j])
+        for i, (qs, qe) in enumerate(oq):
+            exp[i, j] = oracle.count_sorted(sbs, sbe, qs, qe, threads=THREADS, per_query=False)[1]
+    note("  oracle %.1f s" % (time.time() - t0))
+    assert np.array_equal(got2, exp)
     bits.bits_batch_destroy(plan)
 
 
-def test_w4_full_learned_vs_plain_and_sampled():
-    note("case: W4 full 5e7 x 5e7 + MC 1000 x 1e6")
+def test_w4_full_every_count_and_shuffle():
+    note("case: W4 full 5e7 x 5e7, every count and launch shape; MC 1000 x 1e6 vs the oracle")
     lengths, A, B = datagen.w4_sets()
     a_s, a_e = proj(lengths, A)
     b_s, b_e = proj(lengths, B)
-    ref = bits.bits_sort_ref(b_s, b_e, learned=True)
-    c_learn, t_learn = bits.bits_count_per_query(ref, a_s, a_e, launch=RECORDED_LEARNED)
-    c_learn = down(c_learn).copy()
-    c_plain, t_plain = bits.bits_count_per_query(ref, a_s, a_e, launch=RECORDED_PLAIN)
-    assert np.array_equal(down(c_plain), c_learn)
-    oa_s, oa_e = oracle.project(lengths, A.chrom, A.start, A.end)
-    ob_s, ob_e = oracle.project(lengths, B.chrom, B.start, B.end)
+    ref = bits.bits_sort_ref(b_s, b_e, learned=True, train={"epochs": 80})   # bench.py's training
+    oa_s, oa_e = oracle_sets(lengths, A)
+    ob_s, ob_e = oracle_sets(lengths, B)
     del A, B
+    t0 = time.time()
     sbs, sbe = oracle.sort_u32(ob_s), oracle.sort_u32(ob_e)
-    assert np.array_equal(down(ref.sorted_starts()), sbs)
-    assert np.array_equal(down(ref.sorted_ends()), sbe)
-    idx = np.random.default_rng(1).integers(0, len(oa_s), 200_000)
-    exp, _ = oracle.count_sorted(sbs, sbe, oa_s[idx], oa_e[idx], threads=THREADS)
-    assert np.array_equal(c_learn[idx], exp)
-    _, total = oracle.count_sorted(sbs, sbe, oa_s, oa_e, threads=THREADS, per_query=False)
-    assert int(down(t_learn)[0]) == total and int(down(t_plain)[0]) == total
-    nmc = 1_000_000
-    mc = bits.bits_mc_pvalue(ref, a_s[:nmc], a_e[:nmc], lengths, datagen.MC_SEED, 0, 1000, launch=RECORDED_MC)
-    T = down(mc.totals).copy()
+    exp, total = oracle.count_sorted(sbs, sbe, oa_s, oa_e, threads=THREADS)
+    note("  oracle counts %.1f s" % (time.time() - t0))
+    assert np.array_equal(down(ref.sorted_starts()), sbs) and np.array_equal(down(ref.sorted_ends()), sbe)
+    n = check_all_shapes(ref, a_s, a_e, up(exp), total)
+    note("  %d launch shapes equal the oracle on all 5e7 counts" % n)
+    del exp
+    nmc, N = 1_000_000, 1000
     prep = oracle.mc_prepare(lengths, oa_s[:nmc], oa_e[:nmc])
-    for s in (0, 1, 500, 999):
-        assert int(T[s]) == int(oracle.mc_totals(sbs, sbe, prep, datagen.MC_SEED, s, s + 1)[0]), s
+    t0 = time.time()
+    exp_T = oracle.mc_totals(sbs, sbe, prep, datagen.MC_SEED, 0, N, threads=THREADS)
     obs = oracle.count_sorted(sbs, sbe, oa_s[:nmc], oa_e[:nmc], threads=THREADS, per_query=False)[1]
-    assert int(down(mc.observed)[0]) == obs
-    assert (int(down(mc.n_ge)[0]), int(down(mc.n_le)[0])) == oracle.mc_tail(T, obs)
-    # the region-binned path in bench.py's configuration (one pass of 1000 shuffles)
-    from bench import MC_BATCH
-    mb = bits.bits_mc_binned(ref, a_s[:nmc], a_e[:nmc], lengths, datagen.MC_SEED, 0, 1000, batch=MC_BATCH,
-                             launch=RECORDED_MC)
-    assert np.array_equal(down(mb.totals), T)
-    assert int(down(mb.observed)[0]) == obs
-    assert (int(down(mb.n_ge)[0]), int(down(mb.n_le)[0])) == oracle.mc_tail(T, obs)
+    note("  oracle Monte-Carlo %.1f s for 1e9 evaluations" % (time.time() - t0))
+    # the region-binned path in bench.py's configuration (one pass of MC_BATCH shuffles), under
+    # both observed-pass launches bench.py's tuner can pick, and the query-ordered paths
+    for blk in (512, 1024):
+        lp = {"block": blk, "qpl": 1, "depth": 0, "grid": 0, "path": 2}
+        check_mc(bits.bits_mc_binned(ref, a_s[:nmc], a_e[:nmc], lengths, datagen.MC_SEED, 0, N, batch=MC_BATCH,
+                                     launch=lp), exp_T, obs, N)
+        check_mc(bits.bits_mc_pvalue(ref, a_s[:nmc], a_e[:nmc], lengths, datagen.MC_SEED, 0, N, launch=lp),
+                 exp_T, obs, N)
+    check_mc(bits.bits_mc_pvalue(ref, a_s[:nmc], a_e[:nmc], lengths, datagen.MC_SEED, 0, N,
+                                 launch={"block": 256, "qpl": 1, "depth": 13, "grid": 0, "path": 1}), exp_T, obs, N)
     assert bits.bits_get_status(ref) == 0
 
 
 def test_binned_reference_past_2_pow_26():
     """A reference of 7e7 intervals (64 counts of n can pass 2^32, so the search
-    kernel sums each 64-record step in 64 bits): the binned totals equal the
-    query-ordered plain path's, and sampled shuffles equal the oracle's."""
+    kernel sums each 64-record step in 64 bits): every binned total equals the
+    oracle's."""
     note("case: binned, n = 7e7")
     lengths, A, B = datagen.w4_sets(seed=3, n_a=20_000, n_b=70_000_000)
     a_s, a_e = proj(lengths, A)
     b_s, b_e = proj(lengths, B)
     ref = bits.bits_sort_ref(b_s, b_e)
     mb = bits.bits_mc_binned(ref, a_s, a_e, lengths, datagen.MC_SEED, 0, 12, batch=5)
-    mp = bits.bits_mc_pvalue(ref, a_s, a_e, lengths, datagen.MC_SEED, 0, 12, launch=RECORDED_PLAIN)
-    T = down(mb.totals).copy()
-    assert np.array_equal(T, down(mp.totals))
-    assert int(down(mb.observed)[0]) == int(down(mp.observed)[0])
-    ob_s, ob_e = oracle.project(lengths, B.chrom, B.start, B.end)
+    ob_s, ob_e = oracle_sets(lengths, B)
     del B
     sbs, sbe = oracle.sort_u32(ob_s), oracle.sort_u32(ob_e)
-    oa_s, oa_e = oracle.project(lengths, A.chrom, A.start, A.end)
+    oa_s, oa_e = oracle_sets(lengths, A)
     prep = oracle.mc_prepare(lengths, oa_s, oa_e)
-    for s in (0, 11):
-        assert int(T[s]) == int(oracle.mc_totals(sbs, sbe, prep, datagen.MC_SEED, s, s + 1, threads=THREADS)[0]), s
+    exp_T = oracle.mc_totals(sbs, sbe, prep, datagen.MC_SEED, 0, 12, threads=THREADS)
+    obs = oracle.count_sorted(sbs, sbe, oa_s, oa_e, threads=THREADS, per_query=False)[1]
+    check_mc(mb, exp_T, obs, 12)
+    assert bits.bits_get_status(ref) == 0
+
+
+def test_monte_carlo_counter_past_2_pow_32():
+    """Shuffles whose Philox counters g = s * |A| + i all exceed 2^32 (the
+    counter's high word in use): the query-ordered plain and learned paths,
+    the binned path and the paper's orientation (roles swapped: g = s * |B| + j)
+    equal the oracle shuffle by shuffle."""
+    note("case: Monte-Carlo counters past 2^32")
+    lengths, A, B = datagen.w2_sets(seed=5, n_a=1000, n_b=200_000)
+    oa_s, oa_e = oracle_sets(lengths, A)
+    ob_s, ob_e = oracle_sets(lengths, B)
+    s0, s1 = 5_000_000, 5_000_024
+    assert s0 * len(oa_s) > 2**32
+    a_s, a_e, b_s, b_e = up(oa_s), up(oa_e), up(ob_s), up(ob_e)
+    sbs, sbe = oracle.sort_u32(ob_s), oracle.sort_u32(ob_e)
+    exp_T = oracle.mc_totals(sbs, sbe, oracle.mc_prepare(lengths, oa_s, oa_e), 2**33 + 7, s0, s1, threads=8)
+    obs = oracle.count_sorted(sbs, sbe, oa_s, oa_e, per_query=False)[1]
+    ref = bits.bits_sort_ref(b_s, b_e, learned=True, train={"epochs": 20})
+    for lp in ({"block": 1024, "qpl": 1, "depth": 0, "grid": 0, "path": 2},
+               {"block": 256, "qpl": 1, "depth": 13, "grid": 0, "path": 1}):
+        check_mc(bits.bits_mc_pvalue(ref, a_s, a_e, lengths, 2**33 + 7, s0, s1, launch=lp), exp_T, obs, s1 - s0)
+    for batch in (1, 7, 24):
+        check_mc(bits.bits_mc_binned(ref, a_s, a_e, lengths, 2**33 + 7, s0, s1, batch=batch), exp_T, obs, s1 - s0)
+    # the paper's orientation: the 1000-interval set randomised and re-sorted every round,
+    # the 2e5-interval set fixed; the randomised set's counters are s * 1000 + j
+    r0, r1 = 5_000_003, 5_000_013
+    exp_R = oracle.mc_totals(sbs, sbe, oracle.mc_prepare(lengths, oa_s, oa_e), 2**33 + 7, r0, r1)
+    mr = bits.bits_mc_resort(b_s, b_e, a_s, a_e, lengths, 2**33 + 7, r0, r1, batch=4)
+    assert np.array_equal(down(mr.totals), exp_R)
+    assert int(down(mr.observed)[0]) == obs
     assert bits.bits_get_status(ref) == 0

@@ -254,25 +254,62 @@ int main() {
 """
 
 
-def test_philox_matches_rocrand_rounds(tmp_path):
+@pytest.fixture(scope="module")
+def rocrand_rounds(tmp_path_factory):
     """External known-answer source: the installed rocRAND header's own
-    Philox-4x32-10 rounds, compiled for the host and called on the same
-    (counter, key) pairs."""
+    Philox-4x32-10 rounds, compiled for the host.  Returns a function mapping
+    a list of (ctr0, ctr1, ctr2, ctr3, key0, key1) to the four output words."""
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(hipcc):
         pytest.skip("hipcc not available")
-    src = tmp_path / "probe.cpp"
+    d = tmp_path_factory.mktemp("rocrand")
+    src = d / "probe.cpp"
     src.write_text(ROCRAND_PROBE)
-    exe = tmp_path / "probe"
+    exe = d / "probe"
     subprocess.run([hipcc, "-O1", str(src), "-o", str(exe)], check=True, capture_output=True)
+
+    def run(cases):
+        inp = "\n".join(" ".join(str(int(v)) for v in c) for c in cases) + "\n"
+        out = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True).stdout
+        got = [list(map(int, l.split())) for l in out.strip().splitlines()]
+        assert len(got) == len(cases)
+        return got
+    return run
+
+
+def test_philox_matches_rocrand_rounds(rocrand_rounds):
+    """The oracle's Philox-4x32-10 equals rocRAND's rounds on the same
+    (counter, key) pairs, all four words in use."""
     r = np.random.default_rng(11)
     cases = [[0] * 6, [0xFFFFFFFF] * 6] + r.integers(0, 2**32, size=(200, 6), dtype=np.uint64).tolist()
-    inp = "\n".join(" ".join(str(int(v)) for v in c) for c in cases) + "\n"
-    out = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True).stdout
-    got = [list(map(int, l.split())) for l in out.strip().splitlines()]
-    for c, g in zip(cases, got):
+    for c, g in zip(cases, rocrand_rounds(cases)):
         assert list(oracle.philox4x32_10(c[:4], c[4:])) == g
-    assert len(got) == len(cases)
+
+
+@pytest.mark.parametrize("seed,s,na", [(7, 5_000_000, 1000), (2**40 + 12345, 4_294_967, 1001),
+                                       (0xFFFFFFFFFFFFFFFF, 2**33 + 5, 977)])
+def test_mc_placement_counter_past_2_pow_32(rocrand_rounds, seed, s, na):
+    """Monte-Carlo draw (s, i) past the 32-bit counter range (Sec. 3.2's random
+    starts, read as Philox-4x32-10 with counter (lo32 g, hi32 g, 0, 0),
+    g = s * |A| + i, key (lo32 seed, hi32 seed), and start = off +
+    floor(u * span / 2^64) with u = word1:word0): every placement of a shuffle
+    whose counters all exceed 2^32 equals rocRAND's rounds on that counter,
+    mapped to the range in Python integers."""
+    assert s * na >= 2**32
+    r = np.random.default_rng(s % 1000)
+    off = r.integers(0, 2**31, size=na).astype(np.uint32)
+    span = r.integers(1, 2**31, size=na).astype(np.uint32)
+    span[:3] = [1, 2, 0x7FFFFFFF]
+    got = oracle.mc_placements(seed, s, off, span)
+    cases = []
+    for i in range(na):
+        g = s * na + i
+        cases.append([g & 0xFFFFFFFF, g >> 32, 0, 0, seed & 0xFFFFFFFF, seed >> 32])
+    words = rocrand_rounds(cases)
+    for i, w in enumerate(words):
+        u = (w[1] << 32) | w[0]
+        assert int(got[i]) == int(off[i]) + ((u * int(span[i])) >> 64), i
+    assert int(got[0]) == int(off[0])   # span 1: one legal start
 
 
 # ---------------------------------------------------------------- Monte-Carlo
