@@ -65,6 +65,9 @@ typedef enum bits_status {
 #define BITS_PATH_AUTO    0u      /* learned index if the reference has one, else plain */
 #define BITS_PATH_PLAIN   1u      /* LDS Eytzinger top tree + bisection in HBM */
 #define BITS_PATH_LEARNED 2u      /* learned CDF index + windowed search (needs learned ref) */
+#define BITS_PATH_TIERED  3u      /* counting only: LDS top tree, then bisection over the
+                                     32-key node tier (the line heads), then one 128-byte line;
+                                     no model (the index the learned path is measured against) */
 
 /* Launch shape of the search kernels.  A NULL bits_launch* means the
  * library defaults; bits_autotune_count picks one by timing. */
@@ -85,7 +88,7 @@ typedef struct bits_launch {
  *   tree         uint32[2][2^depth]: Eytzinger splitters of B_S then B_E,
  *                node k (1-based BFS order) at [k]; entry 0 unused
  *   rmi          (learned only) 2 x bits_rmi_model (128-byte header + 4096 leaves)
- *   heads        (learned only) uint32[2][hl], line heads of B_S then B_E:
+ *   heads        uint32[2][hl], line heads of B_S then B_E (the 32-key node tier):
  *                H[j] = K[32 j] (first key of each 128-byte line) for j < ceil(n/32),
  *                then 0xFFFFFFFF; hl = 32 * ceil((ceil(n/32) + 32) / 32)
  *   bs, be       uint32[n] each: sorted B_S and B_E (Sec. 2.1, Algorithm 2); the rest
@@ -98,7 +101,7 @@ typedef struct bits_ref {
     uint32_t *be;        /* device: sorted ends */
     uint32_t *tree;      /* device: 2 * 2^depth splitters */
     void *rmi;           /* device: 2 bits_rmi_model (starts, ends) or NULL */
-    uint32_t *heads;     /* device: line heads of B_S, then of B_E (learned only) or NULL */
+    uint32_t *heads;     /* device: line heads of B_S, then of B_E */
     uint32_t *status;    /* device: status word and counters */
     void *block;         /* device: base of the caller's block */
     size_t block_bytes;
@@ -446,7 +449,13 @@ int bits_batch_workspace(const uint64_t *na, uint32_t n_q, uint32_t n_ref, size_
  * are ordered by reference so a workgroup re-stages the LDS top tree only
  * when its reference changes.  Uploads the work list into d_ws (synchronous
  * on `stream`).  refs and the query pointers are host arrays; the device
- * buffers they name must stay valid while the plan is used. */
+ * buffers they name must stay valid while the plan is used.
+ * launch (nullable): block, qpl, depth, grid and path of the persistent
+ * kernel.  path BITS_PATH_LEARNED searches every pair through its
+ * reference's learned index (BITS_E_ARG unless every reference is learned);
+ * BITS_PATH_AUTO (and launch = NULL) picks it when every reference is
+ * learned, else the plain path.  The learned path's fallbacks are counted in
+ * each reference's own counter; interval errors go to refs[0]'s status. */
 int bits_batch_create(const bits_ref *refs, uint32_t n_ref, const uint32_t *const *d_a_start,
                       const uint32_t *const *d_a_end, const uint64_t *na, uint32_t n_q,
                       uint64_t *d_pair_totals, void *d_ws, size_t ws_bytes,
@@ -465,9 +474,21 @@ int bits_batch_destroy(bits_batch_plan *plan);
 /* Times bits_count on the given queries for every candidate launch shape
  * (block 256/512/1024, qpl 1/2/4, LDS depth 8..ref->depth, the given path)
  * with HIP events and writes the fastest to *best and its time to *best_ms.
- * `path` is BITS_PATH_PLAIN or BITS_PATH_LEARNED.  Writes d_total. */
+ * `path` is BITS_PATH_PLAIN, BITS_PATH_LEARNED or BITS_PATH_TIERED.  Writes d_total. */
 int bits_autotune_count(const bits_ref *ref, const uint32_t *d_a_start, const uint32_t *d_a_end,
                         uint64_t na, uint64_t *d_total, uint32_t path, bits_launch *best,
+                        float *best_ms, void *stream);
+
+/* The batch plan's autotuner: builds a plan for every candidate launch shape
+ * of the persistent kernel (block 256/512/1024, qpl 1/2/4, and on the plain
+ * path LDS depth 8..max depth of the references), times its graph replay with
+ * HIP events (one warm-up, best of three) and writes the fastest shape to
+ * *best and its time to *best_ms.  Arguments as bits_batch_create; the
+ * caller may pass a sample of each query set (a prefix) to bound the tuning
+ * time.  Writes d_pair_totals; waits on `stream`. */
+int bits_autotune_batch(const bits_ref *refs, uint32_t n_ref, const uint32_t *const *d_a_start,
+                        const uint32_t *const *d_a_end, const uint64_t *na, uint32_t n_q, uint32_t path,
+                        uint64_t *d_pair_totals, void *d_ws, size_t ws_bytes, bits_launch *best,
                         float *best_ms, void *stream);
 
 /* ---------------------------------------------------------------------- */

@@ -24,7 +24,7 @@ BITS_FLAG_INTERVAL = 0x1
 BITS_FLAG_CHROM = 0x2
 BITS_FLAG_ENUM = 0x4
 BITS_MAX_DEPTH = 13
-BITS_PATH_AUTO, BITS_PATH_PLAIN, BITS_PATH_LEARNED = 0, 1, 2
+BITS_PATH_AUTO, BITS_PATH_PLAIN, BITS_PATH_LEARNED, BITS_PATH_TIERED = 0, 1, 2, 3
 DEPTH_FROM_REF = 0xFFFFFFFF
 
 _u32, _u64, _vp, _sz = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_size_t
@@ -95,6 +95,8 @@ def _load():
         "bits_batch_destroy": ([_vp], ctypes.c_int),
         "bits_autotune_count": ([P(bits_ref), _vp, _vp, _u64, _vp, _u32, P(bits_launch), P(ctypes.c_float), _vp],
                                 ctypes.c_int),
+        "bits_autotune_batch": ([P(bits_ref), _u32, P(_vp), P(_vp), P(_u64), _u32, _u32, _vp, _vp, _sz,
+                                 P(bits_launch), P(ctypes.c_float), _vp], ctypes.c_int),
         "bits_rmi_leaf_grad": ([_vp, _vp, _u32, _vp, _vp, _vp, _vp], ctypes.c_int),
         "bits_rmi_window": ([P(bits_ref), _u32, _vp, _u64, _vp, _vp, _vp], ctypes.c_int),
         "bits_enum_index_bytes": ([_u64, P(_sz)], ctypes.c_int),
@@ -606,6 +608,28 @@ def bits_autotune_count(ref: Ref, a_start, a_end, path: int = BITS_PATH_PLAIN, s
                                     ctypes.byref(ms), _stream(stream)), "bits_autotune_count")
     return best, float(ms.value)
 
+
+def bits_autotune_batch(refs: Sequence[Ref], queries: Sequence[Tuple[torch.Tensor, torch.Tensor]],
+                        path: int = BITS_PATH_PLAIN, stream=None):
+    """Fastest launch shape of the batch plan over these (query set, reference) pairs:
+    every candidate shape's graph replay timed with HIP events.  Pass a prefix of each
+    query set to bound the tuning time."""
+    dev = _device()
+    queries = [(_u32_dev(s, "a_start"), _u32_dev(e, "a_end")) for s, e in queries]
+    nq, nr = len(queries), len(refs)
+    na = [s.numel() for s, _ in queries]
+    ws = _scratch(bits_batch_workspace(na, nr), dev)
+    totals = torch.empty(nq * nr, dtype=torch.uint64, device=dev)
+    rarr = (bits_ref * nr)(*[r.c for r in refs])
+    sp = (_vp * nq)(*[_ptr(s).value for s, _ in queries])
+    ep = (_vp * nq)(*[_ptr(e).value for _, e in queries])
+    nav = (_u64 * nq)(*na)
+    best = bits_launch()
+    ms = ctypes.c_float(0.0)
+    _check(_lib.bits_autotune_batch(rarr, nr, sp, ep, nav, nq, int(path), ctypes.c_void_p(totals.data_ptr()),
+                                    _ptr(ws), ws.numel(), ctypes.byref(best), ctypes.byref(ms), _stream(stream)),
+           "bits_autotune_batch")
+    return best, float(ms.value)
 
 def bits_rmi_info(ref: Ref, stream=None) -> dict:
     st = bits_rmi_stats()

@@ -39,7 +39,7 @@ RefLayout ref_layout(uint64_t n, uint32_t depth, int learned) {
     L.status = o; o = align256(o + kStatusBytes);
     L.tree = o; o = align256(o + (size_t)2 * ((size_t)1 << depth) * sizeof(uint32_t));
     L.rmi = o; o = align256(o + (learned ? 2 * sizeof(bits_rmi_model) : 0));
-    L.heads = o; o = align256(o + (learned ? 2 * heads_len(n) * sizeof(uint32_t) : 0));
+    L.heads = o; o = align256(o + 2 * heads_len(n) * sizeof(uint32_t));
     L.bs = o; o = align256(o + (size_t)n * sizeof(uint32_t));
     L.be = o; o = align256(o + (size_t)n * sizeof(uint32_t));
     L.total = o;
@@ -47,9 +47,9 @@ RefLayout ref_layout(uint64_t n, uint32_t depth, int learned) {
 }
 
 bool ref_ok(const bits_ref* r) {
-    if (!r || !r->status || !r->tree || r->n > 0xFFFFFFFFull) return false;
+    if (!r || !r->status || !r->tree || !r->heads || r->n > 0xFFFFFFFFull) return false;
     if (r->n && (!r->bs || !r->be)) return false;
-    if (r->learned && (!r->rmi || !r->heads)) return false;
+    if (r->learned && !r->rmi) return false;
     return r->depth <= BITS_MAX_DEPTH;
 }
 
@@ -83,16 +83,18 @@ int resolve_launch(const bits_ref* ref, const bits_launch* in, LaunchCfg* out) {
     }
     const uint32_t path = in ? in->path : BITS_PATH_AUTO;
     if (path == BITS_PATH_AUTO) c.path = ref->learned ? BITS_PATH_LEARNED : BITS_PATH_PLAIN;
-    else if (path == BITS_PATH_PLAIN || path == BITS_PATH_LEARNED) c.path = path;
+    else if (path == BITS_PATH_PLAIN || path == BITS_PATH_LEARNED || path == BITS_PATH_TIERED) c.path = path;
     else return BITS_E_ARG;
     if (c.path == BITS_PATH_LEARNED && !ref->learned) return BITS_E_ARG;
     if (c.block != 256 && c.block != 512 && c.block != 1024) return BITS_E_ARG;
     if (c.qpl != 1 && c.qpl != 2 && c.qpl != 4) return BITS_E_ARG;
-    // the learned path's per-wave scratch grows with qpl: step the block down
-    // until one workgroup's scratch fits the device's LDS
-    while (c.path == BITS_PATH_LEARNED && c.block > 256 &&
-           search_lds_bytes(true, 0, (int)c.qpl, c.block) + 1024 > device_lds_per_block())
+    // the per-wave scratch of the learned and tiered paths grows with qpl: step
+    // the block down until one workgroup's LDS fits the device
+    while (c.path != BITS_PATH_PLAIN && c.block > 256 &&
+           count_lds_bytes(c.path, c.depth, (int)c.qpl, c.block) + 1024 > device_lds_per_block())
         c.block >>= 1;
+    if (c.path == BITS_PATH_TIERED && count_lds_bytes(c.path, c.depth, (int)c.qpl, c.block) > device_lds_per_block())
+        return BITS_E_ARG;
     *out = c;
     return BITS_OK;
 }
@@ -112,8 +114,6 @@ SearchArgs make_search_args(const bits_ref* ref, const LaunchCfg& cfg) {
     sa.depth = cfg.depth;
     return sa;
 }
-
-int batch_blocks_per_cu(uint32_t qpl, uint32_t block, uint32_t max_depth);
 
 }  // namespace bits
 
@@ -185,7 +185,7 @@ int bits_ref_init(void* d_block, size_t block_bytes, uint64_t n, uint32_t depth,
     ref->status = (uint32_t*)(b + L.status);
     ref->tree = (uint32_t*)(b + L.tree);
     ref->rmi = learned ? (void*)(b + L.rmi) : nullptr;
-    ref->heads = learned ? (uint32_t*)(b + L.heads) : nullptr;
+    ref->heads = (uint32_t*)(b + L.heads);
     ref->bs = (uint32_t*)(b + L.bs);
     ref->be = (uint32_t*)(b + L.be);
     ref->block = d_block;
@@ -223,9 +223,9 @@ static int finish_ref(const bits_ref* r, const bits_train& tr, void* ws, hipStre
     } else {
         BITS_CHECK_HIP(launch_fill_u32(r->tree, (uint64_t)2 << r->depth, 0u, s));
     }
+    BITS_CHECK_HIP(launch_build_heads(r->bs, r->n, r->heads, s));
+    BITS_CHECK_HIP(launch_build_heads(r->be, r->n, r->heads + heads_len(r->n), s));
     if (r->learned) {
-        BITS_CHECK_HIP(launch_build_heads(r->bs, r->n, r->heads, s));
-        BITS_CHECK_HIP(launch_build_heads(r->be, r->n, r->heads + heads_len(r->n), s));
         bits_rmi_model* m = (bits_rmi_model*)r->rmi;
         if (r->n == 0) {
             BITS_CHECK_HIP(launch_fill_u32((uint32_t*)m, 2 * sizeof(bits_rmi_model) / 4, 0u, s));
@@ -384,6 +384,7 @@ int bits_mc_pvalue(const bits_ref* ref, const uint32_t* d_a_start, const uint32_
     LaunchCfg cfg;
     rc = resolve_launch(ref, launch, &cfg);
     if (rc != BITS_OK) return rc;
+    if (cfg.path == BITS_PATH_TIERED) return BITS_E_ARG;   // a counting-only path
     hipStream_t s = (hipStream_t)stream;
     auto* totals = (unsigned long long*)d_totals;
     auto* obs = (unsigned long long*)d_observed;
@@ -512,6 +513,7 @@ int bits_mc_binned(const bits_ref* ref, const uint32_t* d_a_start, const uint32_
     LaunchCfg cfg;
     rc = resolve_launch(ref, launch, &cfg);
     if (rc != BITS_OK) return rc;
+    if (cfg.path == BITS_PATH_TIERED) return BITS_E_ARG;   // a counting-only path
     hipStream_t s = (hipStream_t)stream;
     auto* totals = (unsigned long long*)d_totals;
     auto* obs = (unsigned long long*)d_observed;
@@ -815,6 +817,7 @@ int bits_decide(const bits_ref* ref, const uint32_t* d_a_start, const uint32_t* 
     LaunchCfg cfg;
     rc = resolve_launch(ref, launch, &cfg);
     if (rc != BITS_OK) return rc;
+    if (cfg.path == BITS_PATH_TIERED) return BITS_E_ARG;   // a counting-only path
     hipStream_t s = (hipStream_t)stream;
     BITS_CHECK_HIP(launch_fill_u32(d_found, 1, 0u, s));
     BITS_CHECK_HIP(launch_fill_u64((unsigned long long*)d_witness, 1, ~0ull, s));
@@ -863,24 +866,33 @@ int bits_batch_create(const bits_ref* refs, uint32_t n_ref, const uint32_t* cons
         return BITS_E_ARG;
     *plan = nullptr;
     uint32_t max_depth = 0;
+    bool all_learned = true;
     for (uint32_t j = 0; j < n_ref; ++j) {
         if (!ref_ok(&refs[j])) return BITS_E_ARG;
         max_depth = std::max(max_depth, refs[j].depth);
+        all_learned = all_learned && refs[j].learned;
     }
     for (uint32_t i = 0; i < n_q; ++i) {
         if (na[i] && (!d_a_start[i] || !d_a_end[i])) return BITS_E_ARG;
         if (na[i] > 0xFFFFFFFFull) return BITS_E_ARG;
     }
-    LaunchCfg cfg{1024u, 2u, max_depth, 0u, BITS_PATH_PLAIN};
+    LaunchCfg cfg{1024u, 2u, max_depth, 0u, all_learned ? BITS_PATH_LEARNED : BITS_PATH_PLAIN};
     if (launch) {
         if (launch->block) cfg.block = launch->block;
         if (launch->qpl) cfg.qpl = launch->qpl;
         if (launch->depth != 0xFFFFFFFFu) cfg.depth = std::min(launch->depth, max_depth);
         cfg.grid = launch->grid;
-        if (launch->path == BITS_PATH_LEARNED) return BITS_E_UNSUPPORTED;
+        if (launch->path == BITS_PATH_PLAIN || launch->path == BITS_PATH_LEARNED) cfg.path = launch->path;
+        else if (launch->path != BITS_PATH_AUTO) return BITS_E_ARG;
     }
+    if (cfg.path == BITS_PATH_LEARNED && !all_learned) return BITS_E_ARG;
     if ((cfg.block != 256 && cfg.block != 512 && cfg.block != 1024) || (cfg.qpl != 1 && cfg.qpl != 2 && cfg.qpl != 4))
         return BITS_E_ARG;
+    // the learned path's per-wave scratch grows with qpl: step the block down until it fits
+    while (cfg.path == BITS_PATH_LEARNED && cfg.block > 256 &&
+           search_lds_bytes(true, 0, (int)cfg.qpl, cfg.block) + 1024 > device_lds_per_block())
+        cfg.block >>= 1;
+    if (cfg.path == BITS_PATH_LEARNED) cfg.depth = 0;
     const uint32_t tile = cfg.block * cfg.qpl;
 
     // Work list ordered by reference, then query set, then tile.
@@ -895,8 +907,7 @@ int bits_batch_create(const bits_ref* refs, uint32_t n_ref, const uint32_t* cons
                 cost.push_back(c * per_q);
             }
     }
-    uint32_t n_wg = cfg.grid ? cfg.grid
-                             : (uint32_t)device_cu_count() * (uint32_t)batch_blocks_per_cu(cfg.qpl, cfg.block, cfg.depth);
+    uint32_t n_wg = cfg.grid ? cfg.grid : (uint32_t)device_cu_count() * (uint32_t)batch_blocks_per_cu(cfg, cfg.depth);
     n_wg = std::max(1u, std::min({n_wg, kMaxBatchWg, (uint32_t)std::max<size_t>(items.size(), 1)}));
     const BatchWs W = batch_ws(n_ref, n_q, items.size(), n_wg);
     if (ws_bytes < W.total) return BITS_E_WORKSPACE;
@@ -912,9 +923,13 @@ int bits_batch_create(const bits_ref* refs, uint32_t n_ref, const uint32_t* cons
         while (w < n_wg && acc >= total * w / n_wg) wg[w++] = (uint32_t)(k + 1);
     }
     std::vector<BatchRef> rtab(n_ref);
-    for (uint32_t j = 0; j < n_ref; ++j)
-        rtab[j] = {refs[j].bs, refs[j].be, refs[j].tree, (uint32_t)refs[j].n, 1u << refs[j].depth,
-                   std::min(refs[j].depth, cfg.depth), 0u};
+    for (uint32_t j = 0; j < n_ref; ++j) {
+        const bits_ref& r = refs[j];
+        const bool L = cfg.path == BITS_PATH_LEARNED;
+        rtab[j] = {r.bs, r.be, r.tree, L ? (const bits_rmi_model*)r.rmi : nullptr, L ? r.heads : nullptr,
+                   L ? r.heads + heads_len(r.n) : nullptr, fallback_counter(&r), (uint32_t)r.n, 1u << r.depth,
+                   std::min(r.depth, cfg.depth), 0u};
+    }
     std::vector<BatchQuery> qtab(n_q);
     for (uint32_t i = 0; i < n_q; ++i) qtab[i] = {d_a_start[i], d_a_end[i], na[i]};
     hipStream_t s = (hipStream_t)stream;
@@ -975,7 +990,9 @@ int bits_autotune_count(const bits_ref* ref, const uint32_t* d_a_start, const ui
                         uint64_t* d_total, uint32_t path, bits_launch* best, float* best_ms, void* stream) {
     int rc = check_queries(ref, d_a_start, d_a_end, na);
     if (rc != BITS_OK) return rc;
-    if (!d_total || !best || !best_ms || (path != BITS_PATH_PLAIN && path != BITS_PATH_LEARNED)) return BITS_E_ARG;
+    if (!d_total || !best || !best_ms ||
+        (path != BITS_PATH_PLAIN && path != BITS_PATH_LEARNED && path != BITS_PATH_TIERED))
+        return BITS_E_ARG;
     if (path == BITS_PATH_LEARNED && !ref->learned) return BITS_E_ARG;
     hipStream_t s = (hipStream_t)stream;
     std::vector<bits_launch> cand;
@@ -1006,6 +1023,69 @@ int bits_autotune_count(const bits_ref* ref, const uint32_t* d_a_start, const ui
             (void)hipEventElapsedTime(&ms, e0, e1);
             tmin = std::min(tmin, ms);
         }
+        if (rc != BITS_OK) break;
+        if (tmin < bestt) {
+            bestt = tmin;
+            bl = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != BITS_OK) return rc;
+    *best = bl;
+    *best_ms = bestt;
+    return BITS_OK;
+}
+
+int bits_autotune_batch(const bits_ref* refs, uint32_t n_ref, const uint32_t* const* d_a_start,
+                        const uint32_t* const* d_a_end, const uint64_t* na, uint32_t n_q, uint32_t path,
+                        uint64_t* d_pair_totals, void* d_ws, size_t ws_bytes, bits_launch* best, float* best_ms,
+                        void* stream) {
+    if (!refs || !n_ref || !best || !best_ms || (path != BITS_PATH_PLAIN && path != BITS_PATH_LEARNED))
+        return BITS_E_ARG;
+    uint32_t max_depth = 0;
+    for (uint32_t j = 0; j < n_ref; ++j) {
+        if (!ref_ok(&refs[j])) return BITS_E_ARG;
+        if (path == BITS_PATH_LEARNED && !refs[j].learned) return BITS_E_ARG;
+        max_depth = std::max(max_depth, refs[j].depth);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<bits_launch> cand;
+    const uint32_t dmin = max_depth > 8 ? 8 : max_depth;
+    for (uint32_t block : {256u, 512u, 1024u})
+        for (uint32_t qpl : {1u, 2u, 4u}) {
+            if (path == BITS_PATH_LEARNED) {
+                cand.push_back({block, qpl, 0u, 0u, path});
+            } else {
+                for (uint32_t d = max_depth + 1; d-- > dmin;) cand.push_back({block, qpl, d, 0u, path});
+            }
+        }
+    hipEvent_t e0, e1;
+    BITS_CHECK_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return BITS_E_HIP;
+    }
+    int rc = BITS_OK;
+    float bestt = 1e30f;
+    bits_launch bl = cand.front();
+    for (const bits_launch& c : cand) {
+        bits_batch_plan* plan = nullptr;
+        rc = bits_batch_create(refs, n_ref, d_a_start, d_a_end, na, n_q, d_pair_totals, d_ws, ws_bytes, &c, stream,
+                               &plan);
+        if (rc != BITS_OK) break;
+        rc = bits_batch_run(plan, stream);   // warm-up
+        float tmin = 1e30f;
+        for (int r = 0; r < 3 && rc == BITS_OK; ++r) {
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = BITS_E_HIP; break; }
+            rc = bits_batch_run(plan, stream);
+            if (rc != BITS_OK) break;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = BITS_E_HIP; break; }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            tmin = std::min(tmin, ms);
+        }
+        bits_batch_destroy(plan);
         if (rc != BITS_OK) break;
         if (tmin < bestt) {
             bestt = tmin;

@@ -15,9 +15,12 @@
 //            ends, in region order: one segment per (shuffle, region);
 //   search   per region (or per share of a region's records when regions
 //            are few): both slices are staged in LDS (B_S with kMargin keys
-//            past the region's end, for ends that cross it), each placement of
-//            each shuffle of the batch is counted by two bisections in LDS, and
-//            the per-shuffle sums are written out;
+//            past the region's end, for ends that cross it), with a table of
+//            slice ranks at equally spaced coordinates (a piecewise-constant
+//            CDF of the slice), and each placement of each shuffle of the
+//            batch is counted by two table lookups, each followed by a
+//            bisection of the few keys of its bucket, all in LDS; the
+//            per-shuffle sums are written out;
 //   reduce   per shuffle: the sums over regions (and shares) are added to the
 //            totals.
 // A region whose slices exceed the LDS capacity (very dense or duplicated
@@ -35,7 +38,13 @@ constexpr uint32_t kMaxCells = 8192;       // cells per chromosome (LDS table of
 constexpr uint32_t kMinShift = 10;         // cells are at least 1 kbp
 constexpr uint32_t kRegionKeys = 8192;     // merged B_S + B_E keys per region (target)
 constexpr uint32_t kMargin = 256;          // B_S keys staged past a region's end
-constexpr uint32_t kSliceWords = 14336;    // LDS slice capacity of the search kernel (56 KiB)
+constexpr uint32_t kSliceWords = 12800;    // LDS slice capacity of the search kernel (50 KiB)
+// Bucket tables of the search kernel: a region's coordinate range is cut
+// into at most kBuckets equal power-of-two buckets; word b of a table packs
+// the slice ranks of bucket b's first and last coordinate + 1 (16 bits each:
+// slices hold fewer than 2^16 keys).
+constexpr uint32_t kBuckets = 1024;
+static_assert(kSliceWords < 65536u, "bucket ranks are 16-bit");
 constexpr uint32_t kBinThreads = 1024;
 // A reference with few regions (a small B) would leave most of the chip idle
 // in the search; each region's records are then split over up to kMaxSplits
@@ -313,11 +322,20 @@ __device__ __forceinline__ void wave_segment_add(uint32_t key, T v, bool valid, 
 // contiguous range of it, 64 records per step; records are grouped by
 // shuffle (pre[s] = first record of shuffle s), so a wave tracks its shuffle
 // by a forward scan and adds per-shuffle sums with wave_segment_add.
+// Bucket geometry of a region [key_lo, key_hi): bucket of x = (x - key_lo) >> sh.
+// On the LDS path, TS / TE hold word b = rank(v_b) | rank(v_{b+1}) << 16,
+// v_b = key_lo + b 2^sh, the ranks being #{S < v} and #{E < v} in the slices.
+struct Buckets {
+    const uint32_t* TS;
+    const uint32_t* TE;
+    uint32_t key_lo, key_hi, sh;
+};
+
 template <bool LDS, typename T>
 __device__ __forceinline__ void bin_count_region(const uint32_t* S, uint32_t ns, const uint32_t* E, uint32_t ne,
                                                  const uint32_t* __restrict__ bs, uint32_t n, uint32_t s_lo,
-                                                 uint32_t e_lo, const uint2* __restrict__ recs, uint64_t na,
-                                                 const uint64_t* pre, const uint32_t* sst, uint32_t nb,
+                                                 uint32_t e_lo, const Buckets& bk, const uint2* __restrict__ recs,
+                                                 uint64_t na, const uint64_t* pre, const uint32_t* sst, uint32_t nb,
                                                  uint64_t q0, uint64_t q1, unsigned long long* acc) {
     const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const uint64_t steps = (q1 - q0 + kWave - 1) / kWave, per = (steps + nw - 1) / nw;
@@ -338,14 +356,24 @@ __device__ __forceinline__ void bin_count_region(const uint32_t* S, uint32_t ns,
         if (valid) {
             while (pre[sl + 1] <= p) ++sl;   // ends at sl < nb: p < pre[nb]
             const uint2 r = recs[(uint64_t)sl * na + sst[sl] + (p - pre[sl])];
-            uint32_t first;
-            if (r.y == 0xFFFFFFFFu) {
+            uint32_t first, last;
+            if (LDS && r.y < bk.key_hi) {
+                // every key <= r.y is below key_hi, so inside the slice: the bucket's keys decide
+                const uint32_t w = bk.TS[(r.y - bk.key_lo) >> bk.sh], lo = w & 0xFFFFu;
+                first = s_lo + lo + rank_in<false>(S + lo, (w >> 16) - lo, r.y);
+            } else if (r.y == 0xFFFFFFFFu) {
                 first = n;
             } else {
                 const uint32_t c = rank_in<false>(S, ns, r.y);
                 first = (c == ns && s_end < n) ? gallop_le(bs, n, s_end, r.y) : s_lo + c;
             }
-            v = (T)(first - (e_lo + rank_in<true>(E, ne, r.x)));
+            if (LDS) {   // key_lo <= r.x < key_hi: the start lies in the region
+                const uint32_t w = bk.TE[(r.x - bk.key_lo) >> bk.sh], lo = w & 0xFFFFu;
+                last = e_lo + lo + rank_in<true>(E + lo, (w >> 16) - lo, r.x);
+            } else {
+                last = e_lo + rank_in<true>(E, ne, r.x);
+            }
+            v = (T)(first - last);
         }
         wave_segment_add<T>(valid ? sl : 0xFFFFFFFFu, v, valid, acc);
         sw = __builtin_amdgcn_readlane(sl, kWave - 1);
@@ -363,6 +391,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_search(
     const uint32_t* __restrict__ seg_cnt, uint32_t nreg_max, uint32_t nb, const uint2* __restrict__ recs,
     uint64_t na, uint32_t splits, unsigned long long* __restrict__ partial) {
     __shared__ uint32_t slice[kSliceWords];
+    __shared__ uint32_t tabs[2 * kBuckets];
     __shared__ uint64_t pre[BITS_MC_BIN_MAX_BATCH + 1];
     __shared__ uint32_t sst[BITS_MC_BIN_MAX_BATCH];
     __shared__ unsigned long long acc[BITS_MC_BIN_MAX_BATCH];
@@ -397,9 +426,24 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_search(
     }
     const uint32_t eo = ns;   // E's first word
     const bool in_lds = (uint64_t)ns + ne <= kSliceWords;
+    // buckets: the least power-of-two width that cuts [key_lo, key_hi) into at most kBuckets
+    Buckets bk{tabs, tabs + kBuckets, d0.key_lo, d1.key_lo, 0u};
+    const uint32_t span = bk.key_hi - bk.key_lo;   // > 0: a region holds at least one cell
+    while (((span - 1u) >> bk.sh) >= kBuckets) ++bk.sh;
+    const uint32_t nbk = ((span - 1u) >> bk.sh) + 1u;
     if (in_lds) {
         for (uint32_t j = threadIdx.x; j < ns; j += blockDim.x) slice[j] = bs[s_lo + j];
         for (uint32_t j = threadIdx.x; j < ne; j += blockDim.x) slice[eo + j] = be[e_lo + j];
+        __syncthreads();
+        for (uint32_t b = threadIdx.x; b < nbk; b += blockDim.x) {
+            const uint64_t v0 = (uint64_t)bk.key_lo + ((uint64_t)b << bk.sh), v1 = v0 + (1ull << bk.sh);
+            const uint32_t s0 = v0 > 0xFFFFFFFFull ? ns : rank_in<true>(slice, ns, (uint32_t)v0);
+            const uint32_t s1 = v1 > 0xFFFFFFFFull ? ns : rank_in<true>(slice, ns, (uint32_t)v1);
+            const uint32_t e0 = v0 > 0xFFFFFFFFull ? ne : rank_in<true>(slice + eo, ne, (uint32_t)v0);
+            const uint32_t e1 = v1 > 0xFFFFFFFFull ? ne : rank_in<true>(slice + eo, ne, (uint32_t)v1);
+            tabs[b] = s0 | (s1 << 16);
+            tabs[kBuckets + b] = e0 | (e1 << 16);
+        }
     }
     __syncthreads();
     // this workgroup's share of the region's records
@@ -408,17 +452,17 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_search(
     // per-step sums fit 32 bits when 64 counts of at most n cannot reach 2^32
     const bool narrow = n < (1u << 26);
     if (in_lds && narrow)
-        bin_count_region<true, uint32_t>(slice, ns, slice + eo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb, q0,
-                                         q1, acc);
+        bin_count_region<true, uint32_t>(slice, ns, slice + eo, ne, bs, n, s_lo, e_lo, bk, recs, na, pre, sst, nb,
+                                         q0, q1, acc);
     else if (in_lds)
-        bin_count_region<true, uint64_t>(slice, ns, slice + eo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb, q0,
-                                         q1, acc);
+        bin_count_region<true, uint64_t>(slice, ns, slice + eo, ne, bs, n, s_lo, e_lo, bk, recs, na, pre, sst, nb,
+                                         q0, q1, acc);
     else if (narrow)
-        bin_count_region<false, uint32_t>(bs + s_lo, ns, be + e_lo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb,
-                                          q0, q1, acc);
+        bin_count_region<false, uint32_t>(bs + s_lo, ns, be + e_lo, ne, bs, n, s_lo, e_lo, bk, recs, na, pre, sst,
+                                          nb, q0, q1, acc);
     else
-        bin_count_region<false, uint64_t>(bs + s_lo, ns, be + e_lo, ne, bs, n, s_lo, e_lo, recs, na, pre, sst, nb,
-                                          q0, q1, acc);
+        bin_count_region<false, uint64_t>(bs + s_lo, ns, be + e_lo, ne, bs, n, s_lo, e_lo, bk, recs, na, pre, sst,
+                                          nb, q0, q1, acc);
     __syncthreads();
     if (threadIdx.x < nb)
         partial[(SPLIT ? (uint64_t)r * splits + part : (uint64_t)r) * nb + threadIdx.x] = acc[threadIdx.x];

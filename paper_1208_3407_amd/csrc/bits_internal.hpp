@@ -111,6 +111,19 @@ __host__ __device__ constexpr size_t search_lds_bytes(bool learned, uint32_t dep
     return learned ? (size_t)(block / kWave) * probe_scratch_words(qpl) * 4u : (size_t)tree_lds_words(depth) * 4u;
 }
 
+// Line-probe scratch of the tiered search per wave: (start, x) of 64 owners
+// and 64 counts (2 * 64 words each) per chain, 2 * QPL chains.
+__host__ __device__ constexpr uint32_t tiered_scratch_words(int qpl) { return 4u * 2u * (uint32_t)qpl * kWave; }
+
+// Counting kernel modes (k_count) and their dynamic LDS: the tiered search
+// stages the top trees and, after them, its per-wave probe scratch.
+enum : int { kModePlain = 0, kModeLearned = 1, kModeTiered = 2 };
+__host__ __device__ constexpr size_t count_lds_bytes(uint32_t path, uint32_t depth, int qpl, uint32_t block) {
+    return path == BITS_PATH_TIERED
+               ? ((size_t)tree_lds_words(depth) + (size_t)(block / kWave) * tiered_scratch_words(qpl)) * 4u
+               : search_lds_bytes(path == BITS_PATH_LEARNED, depth, qpl, block);
+}
+
 // Copy the first 2^d - 1 nodes of both trees into LDS: lds[0..2^d) starts,
 // lds[2^d..2^(d+1)) ends, 1-based BFS order (slot 0 unused).
 __device__ __forceinline__ void stage_tree(uint32_t* lds, const uint32_t* tree, uint32_t stride, uint32_t d) {
@@ -245,6 +258,10 @@ struct BatchRef {        // one reference in the batch table
     const uint32_t* bs;
     const uint32_t* be;
     const uint32_t* tree;
+    const bits_rmi_model* rmi;       // learned path: the two models (else nullptr)
+    const uint32_t* hs;              // learned path: line heads of B_S and B_E
+    const uint32_t* he;
+    unsigned long long* fallbacks;   // the reference's learned-path fallback counter
     uint32_t n, tree_stride, depth, pad;
 };
 struct BatchQuery {
@@ -255,10 +272,13 @@ struct BatchQuery {
 struct BatchItem {       // a tile of one query set against one reference
     uint32_t q, r, begin, count;
 };
+// cfg.path selects the plain (LDS tree + bisection) or the learned search for every pair;
+// the learned path needs every reference learned.
 hipError_t launch_batch(const BatchRef* refs, const BatchQuery* qs, const BatchItem* items,
                         const uint32_t* wg_begin, uint32_t n_wg, uint32_t n_ref, uint32_t max_depth,
                         const LaunchCfg& cfg, unsigned long long* pair_totals, uint32_t* status,
                         hipStream_t s);
+int batch_blocks_per_cu(const LaunchCfg& cfg, uint32_t max_depth);
 
 // sort.hip
 // One segment to sort: n keys in -> out, optionally with one uint32 value per

@@ -284,18 +284,11 @@ constexpr uint32_t kIdleEnd = 0xFFFFFFFFu;
 // bucket are shared by every query landing in it.
 constexpr uint32_t kPlainHotSteps = 3;
 
-template <int QPL>
-__device__ __forceinline__ void icount_plain(const SearchArgs& sa, const uint32_t* lds,
-                                             const uint32_t (&as)[QPL], const uint32_t (&ae)[QPL],
-                                             uint32_t (&cnt)[QPL],
-                                             uint32_t (&fst)[QPL]) {
-    constexpr int NC = 2 * QPL;
-    uint32_t x[NC], base[NC], len[NC];
-#pragma unroll
-    for (int q = 0; q < QPL; ++q) {
-        x[2 * q] = ae[q] + 1u;
-        x[2 * q + 1] = as[q];
-    }
+// The LDS top tree's bucket for each chain: the lower bound #{K_c < x[c]}
+// lies in [base[c], base[c] + len[c]] (the whole array when depth is 0).
+template <int NC>
+__device__ __forceinline__ void tree_bucket(const SearchArgs& sa, const uint32_t* lds, const uint32_t (&x)[NC],
+                                            uint32_t (&base)[NC], uint32_t (&len)[NC]) {
     const uint32_t d = sa.depth;
     if (d) {
         const uint32_t m = 1u << d;
@@ -319,6 +312,21 @@ __device__ __forceinline__ void icount_plain(const SearchArgs& sa, const uint32_
             len[c] = sa.n;
         }
     }
+}
+
+template <int QPL>
+__device__ __forceinline__ void icount_plain(const SearchArgs& sa, const uint32_t* lds,
+                                             const uint32_t (&as)[QPL], const uint32_t (&ae)[QPL],
+                                             uint32_t (&cnt)[QPL],
+                                             uint32_t (&fst)[QPL]) {
+    constexpr int NC = 2 * QPL;
+    uint32_t x[NC], base[NC], len[NC];
+#pragma unroll
+    for (int q = 0; q < QPL; ++q) {
+        x[2 * q] = ae[q] + 1u;
+        x[2 * q + 1] = as[q];
+    }
+    tree_bucket<NC>(sa, lds, x, base, len);
     bisect_multi<NC>(sa.bs, sa.be, base, len, x, kPlainHotSteps);
 #pragma unroll
     for (int q = 0; q < QPL; ++q) {
@@ -590,6 +598,49 @@ __device__ __forceinline__ void icount_heads(const SearchArgs& sa, uint32_t* scr
     }
 }
 
+// Plain search with the 32-key node tier, no model: the line heads
+// H[j] = K[32 j] (1/32 of the array, cached in L2 / the Infinity Cache) sit
+// between the LDS top tree and the sorted array.  The tree narrows the lower
+// bound r = #{K < x} to its bucket [base, base + len]; then
+// j = #{H < x} = ceil(r / 32) lies in [ceil(base / 32), ceil((base + len) / 32)]
+// (every head before that range is < x, every head after it >= x), which is
+// bisected over the heads; one cooperative probe of line j - 1 then gives r
+// (r = 0 when j = 0), as in the head search of the Monte-Carlo path.  `scr`
+// is this wave's probe scratch (tiered_scratch_words(QPL) words).  Must be
+// called by all 64 lanes.
+template <int QPL>
+__device__ __forceinline__ void icount_tiered(const SearchArgs& sa, const uint32_t* lds, uint32_t* scr,
+                                              const uint32_t (&as)[QPL], const uint32_t (&ae)[QPL],
+                                              uint32_t (&cnt)[QPL], uint32_t (&fst)[QPL]) {
+    constexpr int NC = 2 * QPL;
+    uint32_t x[NC], base[NC], len[NC];
+#pragma unroll
+    for (int q = 0; q < QPL; ++q) {
+        x[2 * q] = ae[q] + 1u;
+        x[2 * q + 1] = as[q];
+    }
+    tree_bucket<NC>(sa, lds, x, base, len);
+    uint32_t j[NC], jl[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        j[c] = (uint32_t)(((uint64_t)base[c] + 31u) >> 5);
+        jl[c] = (uint32_t)(((uint64_t)base[c] + len[c] + 31u) >> 5) - j[c];
+    }
+    bisect_multi<NC>(sa.hs, sa.he, j, jl, x, 32u);
+    uint32_t dw[NC], pc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) dw[c] = j[c] ? (j[c] - 1u) * 32u : kNoLine;
+    probe_lines<NC, true>(sa.bs, sa.be, dw, x, pc, scr);
+#pragma unroll
+    for (int q = 0; q < QPL; ++q) {
+        const uint32_t rs = dw[2 * q] == kNoLine ? 0u : dw[2 * q] + pc[2 * q];
+        const uint32_t re = dw[2 * q + 1] == kNoLine ? 0u : dw[2 * q + 1] + pc[2 * q + 1];
+        const uint32_t first = (ae[q] == 0xFFFFFFFFu) ? sa.n : rs;
+        cnt[q] = first - re;
+        fst[q] = first;
+    }
+}
+
 template <int QPL, bool LEARNED>
 __device__ __forceinline__ void icount(const SearchArgs& sa, uint32_t* lds, const uint32_t (&as)[QPL],
                                        const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL], uint32_t (&fst)[QPL]) {
@@ -605,13 +656,15 @@ __device__ __forceinline__ void icount(const SearchArgs& sa, uint32_t* lds, cons
 // loaded by lane (i mod blockDim), so every load of a query round is
 // coalesced.  Totals: uint64 wave sum, one atomic per wave.
 
-template <int QPL, bool LEARNED>
+// MODE: kModePlain (LDS tree + bisection), kModeLearned (learned index,
+// windowed line probe) or kModeTiered (LDS tree + line-head tier + one line).
+template <int QPL, int MODE>
 BITS_SEARCH_KERNEL k_count(SearchArgs sa, const uint32_t* __restrict__ a_start,
                                                 const uint32_t* __restrict__ a_end, uint64_t na,
                                                 uint32_t* __restrict__ counts, uint32_t* __restrict__ firsts,
                                                 unsigned long long* total) {
     extern __shared__ uint32_t lds[];
-    if (!LEARNED) {
+    if (MODE != kModeLearned) {
         stage_tree(lds, sa.tree, sa.tree_stride, sa.depth);
         __syncthreads();
     }
@@ -635,7 +688,11 @@ BITS_SEARCH_KERNEL k_count(SearchArgs sa, const uint32_t* __restrict__ a_start,
             }
         }
         uint32_t fst[QPL];
-        icount<QPL, LEARNED>(sa, lds, as, ae, cnt, fst);
+        if constexpr (MODE == kModeTiered)
+            icount_tiered<QPL>(sa, lds, lds + tree_lds_words(sa.depth) + (threadIdx.x / kWave) * tiered_scratch_words(QPL),
+                               as, ae, cnt, fst);
+        else
+            icount<QPL, MODE == kModeLearned>(sa, lds, as, ae, cnt, fst);
 #pragma unroll
         for (int q = 0; q < QPL; ++q) {
             const uint64_t i = t * tile + (uint64_t)q * blockDim.x + threadIdx.x;
@@ -1222,11 +1279,13 @@ __global__ void k_project(ChromTab ct, const uint32_t* __restrict__ chrom, const
 
 // ------------------------------------------------------------------ batched pairs
 // Each workgroup owns the contiguous item range [wg_begin[w], wg_begin[w+1]);
-// items are sorted by reference, so the LDS tree is re-staged only when the
-// reference changes.  Consecutive logical workgroups run on the same XCD
-// (hardware dispatches workgroups round-robin over the 8 XCDs), so an XCD's
-// L2 sees few distinct references.
-template <int QPL>
+// items are sorted by reference, so (plain path) the LDS tree is re-staged
+// only when the reference changes.  Consecutive logical workgroups run on the
+// same XCD (hardware dispatches workgroups round-robin over the 8 XCDs), so
+// an XCD's L2 sees few distinct references (and, on the learned path, their
+// leaf records).  LEARNED searches every pair through the reference's learned
+// index (leaf model, windowed line probe), with the per-wave scratch in LDS.
+template <int QPL, bool LEARNED>
 __global__ void __launch_bounds__(1024)
     k_batch(const BatchRef* __restrict__ refs, const BatchQuery* __restrict__ qs, const BatchItem* __restrict__ items,
             const uint32_t* __restrict__ wg_begin, uint32_t n_wg, uint32_t n_ref, uint32_t max_depth,
@@ -1243,17 +1302,24 @@ __global__ void __launch_bounds__(1024)
     for (uint32_t it = i0; it < i1; ++it) {
         const BatchItem item = items[it];
         if (item.r != cur) {
-            __syncthreads();
             const BatchRef R = refs[item.r];
             sa.bs = R.bs;
             sa.be = R.be;
             sa.tree = R.tree;
+            sa.rmi = R.rmi;
+            sa.hs = R.hs;
+            sa.he = R.he;
+            sa.status = status;
+            sa.fallbacks = R.fallbacks;
             sa.n = R.n;
             sa.tree_stride = R.tree_stride;
-            sa.depth = min(R.depth, max_depth);
-            stage_tree(lds, sa.tree, sa.tree_stride, sa.depth);
+            sa.depth = LEARNED ? 0u : min(R.depth, max_depth);
+            if (!LEARNED) {
+                __syncthreads();
+                stage_tree(lds, sa.tree, sa.tree_stride, sa.depth);
+                __syncthreads();
+            }
             cur = item.r;
-            __syncthreads();
         }
         const BatchQuery Q = qs[item.q];
         uint32_t as[QPL], ae[QPL], cnt[QPL];
@@ -1271,9 +1337,9 @@ __global__ void __launch_bounds__(1024)
                 ae[q] = as[q];
             }
         }
-        if (sa.n) {
+        if (sa.n) {   // uniform over the workgroup: every item of the loop is one reference
             uint32_t fst[QPL];
-            icount_plain<QPL>(sa, lds, as, ae, cnt, fst);
+            icount<QPL, LEARNED>(sa, lds, as, ae, cnt, fst);
         } else {
 #pragma unroll
             for (int q = 0; q < QPL; ++q) cnt[q] = 0;
@@ -1398,30 +1464,40 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int QPL, bool LEARNED>
+template <int QPL, int MODE>
 static hipError_t launch_count_t(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
                                  uint64_t na, uint32_t* counts, uint32_t* firsts, unsigned long long* total,
                                  hipStream_t s) {
-    const size_t lds = search_lds_bytes(LEARNED, sa.depth, QPL, cfg.block);
+    const size_t lds = count_lds_bytes(cfg.path, sa.depth, QPL, cfg.block);
     const uint64_t tile = (uint64_t)cfg.block * QPL;
-    const void* kern = (const void*)k_count<QPL, LEARNED>;
+    const void* kern = (const void*)k_count<QPL, MODE>;
     const uint32_t grid = persistent_grid(kern, cfg, lds, (na + tile - 1) / tile);
-    hipLaunchKernelGGL((k_count<QPL, LEARNED>), dim3(grid), dim3(cfg.block), lds, s, sa, as, ae, na, counts, firsts,
+    hipLaunchKernelGGL((k_count<QPL, MODE>), dim3(grid), dim3(cfg.block), lds, s, sa, as, ae, na, counts, firsts,
                        total);
     return hipGetLastError();
+}
+
+template <int QPL>
+static hipError_t launch_count_q(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
+                                 uint64_t na, uint32_t* counts, uint32_t* firsts, unsigned long long* total,
+                                 hipStream_t s) {
+    switch (cfg.path) {
+        case BITS_PATH_LEARNED:
+            return launch_count_t<QPL, kModeLearned>(sa, cfg, as, ae, na, counts, firsts, total, s);
+        case BITS_PATH_TIERED:
+            return launch_count_t<QPL, kModeTiered>(sa, cfg, as, ae, na, counts, firsts, total, s);
+        default:
+            return launch_count_t<QPL, kModePlain>(sa, cfg, as, ae, na, counts, firsts, total, s);
+    }
 }
 
 hipError_t launch_count(const SearchArgs& sa, const LaunchCfg& cfg, const uint32_t* as, const uint32_t* ae,
                         uint64_t na, uint32_t* counts, unsigned long long* total, hipStream_t s, uint32_t* firsts) {
     if (!na) return hipSuccess;
-    const bool L = cfg.path == BITS_PATH_LEARNED;
     switch (cfg.qpl) {
-        case 1: return L ? launch_count_t<1, true>(sa, cfg, as, ae, na, counts, firsts, total, s)
-                         : launch_count_t<1, false>(sa, cfg, as, ae, na, counts, firsts, total, s);
-        case 4: return L ? launch_count_t<4, true>(sa, cfg, as, ae, na, counts, firsts, total, s)
-                         : launch_count_t<4, false>(sa, cfg, as, ae, na, counts, firsts, total, s);
-        default: return L ? launch_count_t<2, true>(sa, cfg, as, ae, na, counts, firsts, total, s)
-                          : launch_count_t<2, false>(sa, cfg, as, ae, na, counts, firsts, total, s);
+        case 1: return launch_count_q<1>(sa, cfg, as, ae, na, counts, firsts, total, s);
+        case 4: return launch_count_q<4>(sa, cfg, as, ae, na, counts, firsts, total, s);
+        default: return launch_count_q<2>(sa, cfg, as, ae, na, counts, firsts, total, s);
     }
 }
 
@@ -1586,31 +1662,37 @@ hipError_t launch_project(const uint32_t* chrom_len, uint32_t n_chrom, const uin
     return hipGetLastError();
 }
 
+template <int QPL, bool LEARNED>
+static const void* batch_kernel() {
+    return (const void*)k_batch<QPL, LEARNED>;
+}
+
+static const void* batch_kernel(uint32_t qpl, bool learned) {
+    switch (qpl) {
+        case 1: return learned ? batch_kernel<1, true>() : batch_kernel<1, false>();
+        case 4: return learned ? batch_kernel<4, true>() : batch_kernel<4, false>();
+        default: return learned ? batch_kernel<2, true>() : batch_kernel<2, false>();
+    }
+}
+
+static size_t batch_lds(const LaunchCfg& cfg, uint32_t max_depth) {
+    return search_lds_bytes(cfg.path == BITS_PATH_LEARNED, max_depth, (int)cfg.qpl, cfg.block);
+}
+
 hipError_t launch_batch(const BatchRef* refs, const BatchQuery* qs, const BatchItem* items, const uint32_t* wg_begin,
                         uint32_t n_wg, uint32_t n_ref, uint32_t max_depth, const LaunchCfg& cfg,
                         unsigned long long* pair_totals, uint32_t* status, hipStream_t s) {
-    const size_t lds = tree_lds_words(max_depth) * sizeof(uint32_t);
-    switch (cfg.qpl) {
-        case 1:
-            hipLaunchKernelGGL(k_batch<1>, dim3(n_wg), dim3(cfg.block), lds, s, refs, qs, items, wg_begin, n_wg, n_ref,
-                               max_depth, pair_totals, status);
-            break;
-        case 4:
-            hipLaunchKernelGGL(k_batch<4>, dim3(n_wg), dim3(cfg.block), lds, s, refs, qs, items, wg_begin, n_wg, n_ref,
-                               max_depth, pair_totals, status);
-            break;
-        default:
-            hipLaunchKernelGGL(k_batch<2>, dim3(n_wg), dim3(cfg.block), lds, s, refs, qs, items, wg_begin, n_wg, n_ref,
-                               max_depth, pair_totals, status);
-            break;
-    }
-    return hipGetLastError();
+    const size_t lds = batch_lds(cfg, max_depth);
+    const bool L = cfg.path == BITS_PATH_LEARNED;
+    const void* k = batch_kernel(cfg.qpl, L);
+    void* args[] = {(void*)&refs, (void*)&qs, (void*)&items, (void*)&wg_begin, (void*)&n_wg, (void*)&n_ref,
+                    (void*)&max_depth, (void*)&pair_totals, (void*)&status};
+    return hipLaunchKernel(k, dim3(n_wg), dim3(cfg.block), args, lds, s);
 }
 
-int batch_blocks_per_cu(uint32_t qpl, uint32_t block, uint32_t max_depth) {
-    const size_t lds = tree_lds_words(max_depth) * sizeof(uint32_t);
-    const void* k = qpl == 1 ? (const void*)k_batch<1> : qpl == 4 ? (const void*)k_batch<4> : (const void*)k_batch<2>;
-    return blocks_per_cu(k, (int)block, lds);
+int batch_blocks_per_cu(const LaunchCfg& cfg, uint32_t max_depth) {
+    return blocks_per_cu(batch_kernel(cfg.qpl, cfg.path == BITS_PATH_LEARNED), (int)cfg.block,
+                         batch_lds(cfg, max_depth));
 }
 
 }  // namespace bits

@@ -27,6 +27,9 @@ Workloads (sizes, distributions and seeds):
         reference sets of log-uniform size in [1e4, 5e6].
   * W4  learned index at scale: B = 50M half uniform / half clustered,
         A = 50M uniform; Monte-Carlo over the first 1M of A, 1,000 shuffles.
+  * S   the all-pairs screen of Sec. 3.3 (Fig. 3): 159 annotation tracks of
+        log-uniform size in [1e3, 2e6], each half uniform / half clustered
+        (shared cluster centres), every track both query and reference.
 """
 from __future__ import annotations
 
@@ -174,3 +177,17 @@ def w3_sets(seed: int = 1, n_q: int = 32, n_r: int = 64, q_range=(1_000, 2_000_0
 
 def w4_sets(seed: int = 1, n_a: int = 50_000_000, n_b: int = 50_000_000):
     return w1_sets(seed, n_a, n_b, median_a=200.0, workload=4)
+
+
+def screen_sets(seed: int = 1, n_tracks: int = 159, size_range=(1_000, 2_000_000)):
+    """Tracks of the all-pairs screen: sizes log-uniform in size_range, each a
+    half-uniform / half-clustered mixture around shared centres."""
+    lengths = genome_g24()
+    centres = cluster_centres(rng_for(seed, 6, 9), lengths)
+    r = rng_for(seed, 6, 8)
+    sizes = np.rint(np.exp(r.uniform(np.log(size_range[0]), np.log(size_range[1]), n_tracks))).astype(np.int64)
+    tracks = []
+    for i, n in enumerate(sizes):
+        ri = rng_for(seed, 6, 100 + i)
+        tracks.append(mixture_set(ri, lengths, lognormal_lengths(ri, int(n), 200.0), centres))
+    return lengths, tracks

@@ -66,7 +66,9 @@ def test_ref_init_carves_block_on_host(lib):
     assert lib.bits_ref_init(ctypes.c_void_p(base), ctypes.c_size_t(sz.value - 1), ctypes.c_uint64(100), 13, 0,
                              ctypes.byref(r)) == 4
     assert lib.bits_ref_init(ctypes.c_void_p(base + 4), sz, ctypes.c_uint64(100), 13, 0, ctypes.byref(r)) == 1
-    assert r.rmi is None and r.heads is None
+    # a plain reference has no models but keeps the line heads (the 32-key node tier)
+    hl = ((100 + 31) // 32 + 32 + 31) // 32 * 32
+    assert r.rmi is None and r.heads > r.tree and r.bs >= r.heads + 2 * hl * 4 and r.heads % 256 == 0
     # learned: rmi (2 models of 128 + 4096 * 128 bytes), then the two line-head
     # arrays (ceil(n/32) heads + >= 32 padding, whole 128-byte lines), then B_S, B_E
     n = 100_000

@@ -63,11 +63,11 @@ def count_shapes(ref, path):
 
 def check_all_shapes(ref, a_s, a_e, exp_dev, total):
     """Per-query counts equal the oracle's (compared on the device) and the
-    total equals it, at every candidate shape of both search paths."""
+    total equals it, at every candidate shape of the three counting paths."""
     counts = torch.empty_like(exp_dev)
     tot = torch.empty(1, dtype=torch.uint64, device=DEV)
     n = 0
-    for path in (bits.BITS_PATH_LEARNED, bits.BITS_PATH_PLAIN):
+    for path in (bits.BITS_PATH_LEARNED, bits.BITS_PATH_PLAIN, bits.BITS_PATH_TIERED):
         for lp in count_shapes(ref, path):
             bits.bits_count_per_query(ref, a_s, a_e, launch=lp, counts=counts, total=tot)
             assert torch.equal(counts, exp_dev), lp

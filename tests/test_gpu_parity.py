@@ -45,6 +45,10 @@ LAUNCHES = [
     {"path": bits.BITS_PATH_PLAIN, "block": 256, "qpl": 1, "depth": 0},
     {"path": bits.BITS_PATH_PLAIN, "block": 512, "qpl": 4, "depth": 9},
     {"path": bits.BITS_PATH_PLAIN, "block": 1024, "qpl": 2, "depth": 13, "grid": 7},
+    {"path": bits.BITS_PATH_TIERED},
+    {"path": bits.BITS_PATH_TIERED, "block": 256, "qpl": 4, "depth": 0},
+    {"path": bits.BITS_PATH_TIERED, "block": 1024, "qpl": 1, "depth": 13, "grid": 5},
+    {"path": bits.BITS_PATH_TIERED, "block": 1024, "qpl": 4, "depth": 13},
 ]
 
 
@@ -99,7 +103,7 @@ def test_edge_cases():
     assert c.numel() == 0 and int(down(t)[0]) == 0
     # all keys equal (every digit constant: sort copies), duplicates
     ref2 = bits.bits_sort_ref(up([7] * 5000), up([7] * 5000), learned=True, train={"epochs": 5})
-    for lp in ({"path": 1}, {"path": 2}):
+    for lp in ({"path": 1}, {"path": 2}, {"path": 3}):
         c, _ = bits.bits_count_per_query(ref2, up([0, 7, 8, 0]), up([6, 7, 9, 100]), launch=lp)
         assert list(down(c)) == [0, 5000, 0, 5000]
     # extreme coordinates: end = 2^32 - 1 and start = 0
@@ -108,7 +112,7 @@ def test_edge_cases():
     qs, qe = [0, M, 3, M - 1], [M, M, 4, M - 1]
     ref3 = bits.bits_sort_ref(up(bs), up(be), learned=True, train={"epochs": 5})
     exp, _ = oracle.count_bruteforce(qs, qe, bs, be)
-    for lp in ({"path": 1}, {"path": 2}):
+    for lp in ({"path": 1}, {"path": 2}, {"path": 3}):
         c, _ = bits.bits_count_per_query(ref3, up(qs), up(qe), launch=lp)
         assert np.array_equal(down(c), exp), lp
     # golden fixtures (contained intervals, touching endpoints)
@@ -225,15 +229,42 @@ def test_batch_pairs_graph_replay():
     for i, (qs, qe) in enumerate(qo):
         for j, (rs, re_) in enumerate(ro):
             exp[i, j] = oracle.counter(qs, qe, rs, re_)[1]
-    for lp in (None, {"block": 256, "qpl": 1, "depth": 5}, {"block": 1024, "qpl": 4}):
-        plan = bits.bits_batch_create(refs, qd, launch=lp)
+    lrefs = bits.bits_sort_refs(rd, learned=True, train={"epochs": 10})
+    for rr, lp in ((refs, None), (refs, {"block": 256, "qpl": 1, "depth": 5}), (refs, {"block": 1024, "qpl": 4}),
+                   (lrefs, None), (lrefs, {"block": 512, "qpl": 2, "path": bits.BITS_PATH_LEARNED}),
+                   (lrefs, {"block": 1024, "qpl": 4, "path": bits.BITS_PATH_LEARNED}),
+                   (lrefs, {"block": 256, "qpl": 1, "depth": 13, "path": bits.BITS_PATH_PLAIN})):
+        plan = bits.bits_batch_create(rr, qd, launch=lp)
         for rep in range(3):
             tot = bits.bits_batch_run(plan)
             got = down(tot).reshape(len(Q), len(R))
             assert np.array_equal(got, exp), (lp, rep)
             # eager work between replays
-            bits.bits_count(refs[0], qd[0][0], qd[0][1])
+            bits.bits_count(rr[0], qd[0][0], qd[0][1])
             torch.cuda.synchronize()
+        bits.bits_batch_destroy(plan)
+    # the learned path needs every reference learned
+    with pytest.raises(bits.BitsError):
+        bits.bits_batch_create(refs, qd, launch={"path": bits.BITS_PATH_LEARNED})
+    assert bits.bits_get_status(lrefs[0]) == 0
+
+
+def test_batch_autotuner():
+    """bits_autotune_batch times every candidate shape of the batch plan; the
+    shape it returns gives the oracle's pair totals, on both paths."""
+    note("case: batch autotuner")
+    lengths, Q, R = datagen.w3_sets(seed=4, n_q=4, n_r=5, q_range=(100, 20_000), r_range=(1000, 60_000))
+    qd = [bits.bits_project(lengths, up(S.chrom), up(S.start), up(S.end)) for S in Q]
+    rd = [bits.bits_project(lengths, up(S.chrom), up(S.start), up(S.end)) for S in R]
+    qo = [oracle.project(lengths, S.chrom, S.start, S.end) for S in Q]
+    ro = [oracle.project(lengths, S.chrom, S.start, S.end) for S in R]
+    exp = np.array([[oracle.counter(qs, qe, rs, re_)[1] for rs, re_ in ro] for qs, qe in qo], np.uint64)
+    lrefs = bits.bits_sort_refs(rd, learned=True, train={"epochs": 10})
+    for path in (bits.BITS_PATH_PLAIN, bits.BITS_PATH_LEARNED):
+        best, ms = bits.bits_autotune_batch(lrefs, qd, path=path)
+        assert ms > 0 and best.path == path and best.block in (256, 512, 1024) and best.qpl in (1, 2, 4)
+        plan = bits.bits_batch_create(lrefs, qd, launch=best.as_dict())
+        assert np.array_equal(down(bits.bits_batch_run(plan)).reshape(len(Q), len(R)), exp), best.as_dict()
         bits.bits_batch_destroy(plan)
 
 

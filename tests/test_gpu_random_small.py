@@ -51,7 +51,7 @@ def test_random_counts_both_paths(case):
     learned = nb > 0
     ref = bits.bits_sort_ref(up(b_s), up(b_e), depth=int(r.integers(0, 14)), learned=learned,
                              train={"epochs": int(r.choice([0, 20]))})
-    paths = [bits.BITS_PATH_PLAIN] + ([bits.BITS_PATH_LEARNED] if learned else [])
+    paths = [bits.BITS_PATH_PLAIN, bits.BITS_PATH_TIERED] + ([bits.BITS_PATH_LEARNED] if learned else [])
     for path in paths:
         for qpl in (1, 2, 4):
             lp = {"path": path, "qpl": qpl, "block": int(r.choice([256, 512, 1024]))}
@@ -91,14 +91,16 @@ def test_random_monte_carlo(case):
         assert (int(down(mc.n_ge)[0]), int(down(mc.n_le)[0])) == oracle.mc_tail(exp, obs)
 
 
-def test_random_batch_shapes():
+@pytest.mark.parametrize("learned", [False, True])
+def test_random_batch_shapes(learned):
     r = np.random.default_rng(77)
     qsets = [rand_set(r, int(n), 10**6, 300) for n in (0, 1, 33, 5000, 70_000)]
     rsets = [rand_set(r, int(n), 10**6, 300) for n in (0, 1, 32, 4097, 50_000, 3)]
-    refs = bits.bits_sort_refs([(up(s), up(e)) for s, e in rsets])
-    plan = bits.bits_batch_create(refs, [(up(s), up(e)) for s, e in qsets], launch={"block": 256, "qpl": 2})
-    got = down(bits.bits_batch_run(plan)).reshape(len(qsets), len(rsets))
-    for i, (qs, qe) in enumerate(qsets):
-        for j, (rs, re_) in enumerate(rsets):
-            assert int(got[i, j]) == oracle.counter(qs, qe, rs, re_)[1], (i, j)
-    bits.bits_batch_destroy(plan)
+    refs = bits.bits_sort_refs([(up(s), up(e)) for s, e in rsets], learned=learned, train={"epochs": 5})
+    for lp in ({"block": 256, "qpl": 2}, {"block": 1024, "qpl": 1}, {"block": 512, "qpl": 4, "grid": 3}):
+        plan = bits.bits_batch_create(refs, [(up(s), up(e)) for s, e in qsets], launch=lp)
+        got = down(bits.bits_batch_run(plan)).reshape(len(qsets), len(rsets))
+        for i, (qs, qe) in enumerate(qsets):
+            for j, (rs, re_) in enumerate(rsets):
+                assert int(got[i, j]) == oracle.counter(qs, qe, rs, re_)[1], (lp, i, j)
+        bits.bits_batch_destroy(plan)

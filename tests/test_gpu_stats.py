@@ -155,3 +155,36 @@ def test_paper_orientation_interval_outside_chromosome():
         en_ = st_ + len4[keep] - np.uint32(1)
         assert int(t[s]) == oracle.counter(a_s, a_e, st_, en_)[1], s
     assert int(down(mc.observed)[0]) == oracle.counter(a_s, a_e, b_s[keep], b_e[keep])[1]
+
+
+def test_all_pairs_screen_small():
+    """The all-pairs screen of Sec. 3.3 at a small scale (6 tracks, 36 pairs,
+    15 rounds): observed counts of all pairs from one batch launch, and every
+    pair's Monte-Carlo totals, median, enrichment and p-value, against the
+    oracle pair by pair."""
+    note("case: all-pairs screen, 6 tracks")
+    from paper_1208_3407_amd import screen
+    lengths, tracks = datagen.screen_sets(seed=3, n_tracks=6, size_range=(300, 6000))
+    td = [bits.bits_project(lengths, up(T.chrom), up(T.start), up(T.end)) for T in tracks]
+    to = [oracle.project(lengths, T.chrom, T.start, T.end) for T in tracks]
+    refs = bits.bits_sort_refs(td)
+    plan = bits.bits_batch_create(refs, td)
+    observed = down(bits.bits_batch_run(plan)).reshape(6, 6)
+    bits.bits_batch_destroy(plan)
+    N = 15
+    for i in range(6):
+        prep = oracle.mc_prepare(lengths, to[i][0], to[i][1])
+        for j in range(6):
+            sbs, sbe = np.sort(to[j][0]), np.sort(to[j][1])
+            obs = oracle.counter(to[i][0], to[i][1], to[j][0], to[j][1])[1]
+            assert int(observed[i, j]) == obs, (i, j)
+            exp_T = oracle.mc_totals(sbs, sbe, prep, screen.MC_SEED, 0, N)
+            mc, lo, hi = screen.mc_pair(refs[j], td[i], lengths, N, batch=screen.pass_batch(len(tracks[i])))
+            assert np.array_equal(down(mc.totals), exp_T), (i, j)
+            s = screen.summarise(mc, lo, hi, N)
+            olo, ohi = oracle.mc_median(exp_T)
+            assert s["observed"] == obs and s["median"] == (olo + ohi) / 2
+            ge, le = oracle.mc_tail(exp_T, obs)
+            assert s["p_upper"] == oracle.pvalue(ge, N)
+            e = oracle.enrichment(obs, olo, ohi)
+            assert s["enrichment_log2"] == e or (np.isnan(e) and np.isnan(s["enrichment_log2"]))
