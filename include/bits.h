@@ -55,6 +55,7 @@ typedef enum bits_status {
 
 #define BITS_MAX_CHROM   256u     /* chromosomes per genome for projection / Monte-Carlo */
 #define BITS_MC_BIN_MAX_BATCH 1024u /* shuffles per pass of bits_mc_binned */
+#define BITS_NOALLOC_MAX_QUERIES (1u << 20) /* queries per call of bits_mc_pvalue_noalloc */
 #define BITS_MAX_DEPTH   13u      /* Eytzinger top-tree levels held in LDS */
 #define BITS_RMI_LEAVES  4096u    /* leaf models per learned index */
 #define BITS_RMI_HIDDEN  16u      /* hidden ReLU units per leaf model */
@@ -286,6 +287,25 @@ int bits_mc_pvalue(const bits_ref *ref, const uint32_t *d_a_start, const uint32_
                    uint64_t s0, uint64_t s1, void *d_ws, size_t ws_bytes, uint64_t *d_totals,
                    uint64_t *d_observed, uint64_t *d_n_ge, uint64_t *d_n_le,
                    const bits_launch *launch, void *stream);
+
+/* bits_mc_pvalue without the caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, outputs, flags and
+ * results bit for bit as bits_mc_pvalue, less d_ws and ws_bytes: the query
+ * table lives in a device array of the library, about 16 MiB, that each GPU
+ * the library runs on holds until the process ends.  Its device address is
+ * looked up on the first call on a device; after that the call allocates
+ * nothing and calls no allocating routine.
+ *   na <= BITS_NOALLOC_MAX_QUERIES, else BITS_E_WORKSPACE (nothing enqueued)
+ *   stream must belong to the current device, else BITS_E_ARG
+ * Every call on one GPU shares that array (each call rebuilds the table it
+ * reads, so nothing carries over): calls that overlap on one GPU, on
+ * different streams or from different threads, race and give wrong totals. */
+int bits_mc_pvalue_noalloc(const bits_ref *ref, const uint32_t *d_a_start, const uint32_t *d_a_end,
+                           uint64_t na, const uint32_t *chrom_len, uint32_t n_chrom, uint64_t seed,
+                           uint64_t s0, uint64_t s1, uint64_t *d_totals, uint64_t *d_observed,
+                           uint64_t *d_n_ge, uint64_t *d_n_le, const bits_launch *launch,
+                           void *stream);
 
 /* Workspace bytes of bits_mc_binned for na queries (na < 2^32) against a
  * reference of n intervals on the genome chrom_len[n_chrom], with `batch`

@@ -24,6 +24,7 @@ BITS_FLAG_INTERVAL = 0x1
 BITS_FLAG_CHROM = 0x2
 BITS_FLAG_ENUM = 0x4
 BITS_MAX_DEPTH = 13
+BITS_NOALLOC_MAX_QUERIES = 1 << 20
 BITS_PATH_AUTO, BITS_PATH_PLAIN, BITS_PATH_LEARNED, BITS_PATH_TIERED = 0, 1, 2, 3
 DEPTH_FROM_REF = 0xFFFFFFFF
 
@@ -87,6 +88,8 @@ def _load():
         "bits_mc_workspace": ([_u64, P(_sz)], ctypes.c_int),
         "bits_mc_pvalue": ([P(bits_ref), _vp, _vp, _u64, P(_u32), _u32, _u64, _u64, _u64, _vp, _sz, _vp, _vp,
                             _vp, _vp, P(bits_launch), _vp], ctypes.c_int),
+        "bits_mc_pvalue_noalloc": ([P(bits_ref), _vp, _vp, _u64, P(_u32), _u32, _u64, _u64, _u64, _vp, _vp, _vp,
+                                    _vp, P(bits_launch), _vp], ctypes.c_int),
         "bits_pvalue": ([_u64, _u64], ctypes.c_double),
         "bits_batch_workspace": ([P(_u64), _u32, _u32, P(_sz)], ctypes.c_int),
         "bits_batch_create": ([P(bits_ref), _u32, P(_vp), P(_vp), P(_u64), _u32, _vp, _vp, _sz, P(bits_launch),
@@ -429,6 +432,26 @@ def bits_mc_pvalue(ref: Ref, a_start, a_end, chrom_len, seed: int, s0: int, s1: 
                                ctypes.c_void_p(out.observed.data_ptr()), ctypes.c_void_p(out.n_ge.data_ptr()),
                                ctypes.c_void_p(out.n_le.data_ptr()), _lp(launch), _stream(stream)), "bits_mc_pvalue")
     out._keepalive = workspace
+    return out
+
+
+def bits_mc_pvalue_noalloc(ref: Ref, a_start, a_end, chrom_len, seed: int, s0: int, s1: int, out: MCResult,
+                           launch=None, stream=None) -> MCResult:
+    """bits_mc_pvalue with its query table in the library's own device array (no workspace,
+    no allocation in the call); `out` is required (its tensors are the call's outputs)."""
+    _device()
+    a_start, a_end = _u32_dev(a_start, "a_start"), _u32_dev(a_end, "a_end")
+    if out is None:
+        raise BitsError("bits_mc_pvalue_noalloc: out is required")
+    _check_mc_args(a_start, a_end, s0, s1, out)
+    if a_start.numel() > BITS_NOALLOC_MAX_QUERIES:
+        raise BitsError("bits_mc_pvalue_noalloc: at most %d queries" % BITS_NOALLOC_MAX_QUERIES)
+    cl = _host_u32(chrom_len)
+    _check(_lib.bits_mc_pvalue_noalloc(ctypes.byref(ref.c), _ptr(a_start), _ptr(a_end), a_start.numel(), cl, len(cl),
+                                       int(seed), int(s0), int(s1), _ptr(out.totals),
+                                       ctypes.c_void_p(out.observed.data_ptr()), ctypes.c_void_p(out.n_ge.data_ptr()),
+                                       ctypes.c_void_p(out.n_le.data_ptr()), _lp(launch), _stream(stream)),
+           "bits_mc_pvalue_noalloc")
     return out
 
 

@@ -363,7 +363,14 @@ int bits_mc_workspace(uint64_t na, size_t* bytes) {
     return BITS_OK;
 }
 
-int bits_mc_pvalue(const bits_ref* ref, const uint32_t* d_a_start, const uint32_t* d_a_end, uint64_t na,
+}  // extern "C"
+
+namespace {
+
+// The body of bits_mc_pvalue and bits_mc_pvalue_noalloc: d_ws is the query
+// table (bits_mc_workspace(na) bytes), from the caller or the library's own
+// device array.
+int mc_pvalue_impl(const bits_ref* ref, const uint32_t* d_a_start, const uint32_t* d_a_end, uint64_t na,
                    const uint32_t* chrom_len, uint32_t n_chrom, uint64_t seed, uint64_t s0, uint64_t s1,
                    void* d_ws, size_t ws_bytes, uint64_t* d_totals, uint64_t* d_observed, uint64_t* d_n_ge,
                    uint64_t* d_n_le, const bits_launch* launch, void* stream) {
@@ -407,6 +414,68 @@ int bits_mc_pvalue(const bits_ref* ref, const uint32_t* d_a_start, const uint32_
     }
     BITS_CHECK_HIP(launch_mc_tail(totals, ns, obs, (unsigned long long*)d_n_ge, (unsigned long long*)d_n_le, s));
     return BITS_OK;
+}
+
+// Query table of bits_mc_pvalue_noalloc for up to BITS_NOALLOC_MAX_QUERIES
+// queries.  In host code `scratch` only names the symbol: its device address
+// (one per GPU) comes from hipGetSymbolAddress, taken once per device.
+constexpr size_t kNoallocBytes =
+    4 * ((BITS_NOALLOC_MAX_QUERIES * sizeof(uint32_t) + 255) & ~(size_t)255) +
+    2 * ((BITS_MAX_CHROM * sizeof(uint32_t) + 255) & ~(size_t)255);
+__device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's address of `scratch`, looked up on its first use.  The
+// stream must belong to the current device.
+int noalloc_scratch(void* stream, void** out) {
+    int dev = 0;
+    BITS_CHECK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return BITS_E_ARG;
+    if (stream) {
+        int sdev = -1;
+        BITS_CHECK_HIP(hipStreamGetDevice((hipStream_t)stream, &sdev));
+        if (sdev != dev) return BITS_E_ARG;
+    }
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        BITS_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return BITS_E_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BITS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bits_mc_pvalue(const bits_ref* ref, const uint32_t* d_a_start, const uint32_t* d_a_end, uint64_t na,
+                   const uint32_t* chrom_len, uint32_t n_chrom, uint64_t seed, uint64_t s0, uint64_t s1,
+                   void* d_ws, size_t ws_bytes, uint64_t* d_totals, uint64_t* d_observed, uint64_t* d_n_ge,
+                   uint64_t* d_n_le, const bits_launch* launch, void* stream) {
+    return mc_pvalue_impl(ref, d_a_start, d_a_end, na, chrom_len, n_chrom, seed, s0, s1, d_ws, ws_bytes, d_totals,
+                          d_observed, d_n_ge, d_n_le, launch, stream);
+}
+
+int bits_mc_pvalue_noalloc(const bits_ref* ref, const uint32_t* d_a_start, const uint32_t* d_a_end, uint64_t na,
+                           const uint32_t* chrom_len, uint32_t n_chrom, uint64_t seed, uint64_t s0, uint64_t s1,
+                           uint64_t* d_totals, uint64_t* d_observed, uint64_t* d_n_ge, uint64_t* d_n_le,
+                           const bits_launch* launch, void* stream) {
+    if (na > BITS_NOALLOC_MAX_QUERIES) return BITS_E_WORKSPACE;
+    size_t need = 0;
+    int rc = bits_mc_workspace(na, &need);
+    if (rc != BITS_OK) return rc;
+    if (need > kNoallocBytes) return BITS_E_WORKSPACE;
+    void* ws = nullptr;
+    rc = noalloc_scratch(stream, &ws);
+    if (rc != BITS_OK) return rc;
+    return mc_pvalue_impl(ref, d_a_start, d_a_end, na, chrom_len, n_chrom, seed, s0, s1, ws, kNoallocBytes, d_totals,
+                          d_observed, d_n_ge, d_n_le, launch, stream);
 }
 
 // ---------------------------------------------------------------- Monte-Carlo binned by region

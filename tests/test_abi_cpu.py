@@ -172,3 +172,15 @@ def test_monte_carlo_wrappers_refuse_mismatched_buffers():
         bits._check_mc_args(a, a, 0, 8, bits.MCResult(torch.zeros(8, dtype=torch.int32), u64(1), u64(1), u64(1)))
     with pytest.raises(bits.BitsError, match="uint64"):
         bits._check_mc_args(a, a, 0, 4, bits.MCResult(u64(16)[::2], u64(1), u64(1), u64(1)))
+
+
+def test_noalloc_monte_carlo_limit_checked_on_host(lib):
+    """bits_mc_pvalue_noalloc refuses more queries than its device array
+    holds before it looks at anything else (no device is touched)."""
+    U64 = ctypes.c_uint64
+    lim = int(re.search(r"#define BITS_NOALLOC_MAX_QUERIES \(1u << (\d+)\)", open(HEADER).read()).group(1))
+    lens = (ctypes.c_uint32 * 1)(1000)
+    assert lib.bits_mc_pvalue_noalloc(None, None, None, U64((1 << lim) + 1), lens, 1, U64(7), U64(0), U64(4),
+                                      None, None, None, None, None, None) == 4
+    assert lib.bits_mc_pvalue_noalloc(None, None, None, U64(2**40), lens, 1, U64(7), U64(0), U64(4),
+                                      None, None, None, None, None, None) == 4
