@@ -57,9 +57,9 @@ HBM_PEAK_GBS = 8000.0
 LDS_PEAK_GBS = 128 * 256 * 2.4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_bin_w4.json")
 # launch shapes the autotuner picked on MI355X for this workload (used with --no-autotune)
-RECORDED_LEARNED = {"block": 1024, "qpl": 1, "depth": 0, "grid": 0, "path": 2}
+RECORDED_LEARNED = {"block": 256, "qpl": 1, "depth": 0, "grid": 0, "path": 2}
 RECORDED_PLAIN = {"block": 256, "qpl": 1, "depth": 13, "grid": 0, "path": 1}
-RECORDED_TIERED = {"block": 1024, "qpl": 1, "depth": 13, "grid": 0, "path": 3}
+RECORDED_TIERED = {"block": 256, "qpl": 1, "depth": 13, "grid": 0, "path": 3}
 RECORDED_MC = {"block": 1024, "qpl": 1, "depth": 0, "grid": 0, "path": 2}
 KERNEL_SOURCES = ["paper_1208_3407_amd/csrc/binned.hip", "paper_1208_3407_amd/csrc/bits_internal.hpp"]
 
