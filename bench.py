@@ -55,6 +55,8 @@ BYTES_PER_EVAL_LEARNED = 256.0
 HBM_PEAK_GBS = 8000.0
 # LDS: 128 bytes per clock per CU, 256 CUs, 2.4 GHz
 LDS_PEAK_GBS = 128 * 256 * 2.4
+# VALU: four 16-lane SIMDs per CU retire one wave64 instruction per clock between them
+VALU_PEAK_G = 256 * 2.4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_bin_w4.json")
 # launch shapes the autotuner picked on MI355X for this workload (used with --no-autotune)
 RECORDED_LEARNED = {"block": 256, "qpl": 1, "depth": 0, "grid": 0, "path": 2}
@@ -96,6 +98,20 @@ def load_counters(kernel, placements_per_launch):
     lds = t.get("lds_instructions_per_placement", {}).get(kernel)
     return (None if b is None else float(b) * placements_per_launch,
             None if lds is None else float(lds) * placements_per_launch)
+
+
+def load_valu(kernel, placements_per_launch):
+    """VALU wave-instructions per launch of a binned kernel from the committed counter
+    summary, if it was taken on the current kernel source (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    v = t.get("valu_instructions_per_placement", {}).get(kernel)
+    return None if v is None else float(v) * placements_per_launch
 
 
 def host_cpu():
@@ -584,6 +600,8 @@ def main():
     pass_ms = (stage_ms["place"] + stage_ms["search"] + stage_ms["reduce"]) / passes
     _, lds_instr = load_counters("k_bin_search", placements)
     lds_ach = None if lds_instr is None else lds_instr * 256.0 / (launch_ms["k_bin_search"] / 1e3) / 1e9
+    valu_instr = load_valu("k_bin_search", placements)
+    valu_ach = None if valu_instr is None else valu_instr / (launch_ms["k_bin_search"] / 1e3) / 1e9
     learned_achieved = BYTES_PER_EVAL_LEARNED * N_SHUF * N_MC / (t_mc_learned / 1e3) / 1e9
 
     configs = None if args.no_configs else other_configs(bits, dev, timed, train)
@@ -640,6 +658,12 @@ def main():
                          "unit": "GB/s", "frac": None if lds_ach is None else lds_ach / LDS_PEAK_GBS,
                          "launch_ms": launch_ms["k_bin_search"],
                          "bytes": "LDS instructions per launch (counters) x 256 B (64 lanes x 4 B)"},
+        "roofline_valu": {"bound": "alu", "kernel": "k_bin_search", "achieved": valu_ach, "peak": VALU_PEAK_G,
+                          "unit": "G wave-instructions/s",
+                          "frac": None if valu_ach is None else valu_ach / VALU_PEAK_G,
+                          "launch_ms": launch_ms["k_bin_search"],
+                          "bytes": "VALU wave-instructions per launch (counters); peak: one wave64 VALU "
+                                   "instruction per CU per clock, 256 CUs, 2.4 GHz"},
         "roofline_learned_mc": {"bound": "hbm", "kernel": "k_mc_sorted (query-ordered learned-index Monte-Carlo, "
                                 "outside the timed region)", "achieved": learned_achieved, "peak": HBM_PEAK_GBS,
                                 "unit": "GB/s", "frac": learned_achieved / HBM_PEAK_GBS,
