@@ -499,7 +499,7 @@ def main():
     gain["speedup_training"] = gain["init_only"]["ms"] / gain["trained"]["ms"]
     # training points per leaf: window against setup time (80 epochs)
     sweep = []
-    for pts in (256, 1024, 2048):
+    for pts in (64, 128, 256, 1024, 2048):
         tr = {"epochs": args.epochs, "max_points": pts}
         ts = timed(lambda: bits.bits_sort_ref(b_s, b_e, learned=True, train=tr, ref=ref, workspace=ws), reps=2)
         st = bits.bits_rmi_info(ref)

@@ -119,36 +119,94 @@ __global__ void k_rmi_bounds(Pair2 P, uint64_t n) {
 }
 
 // ---------------------------------------------------------------- leaf training
-// One wave trains one leaf.  Its up to 2048 training points sit in the
-// wave's LDS slice; the 49 parameters are uniform across the wave; lane
-// k < 49 owns parameter k's Adam moments.  Reductions are wave-only (row
-// rotations, then two lane exchanges), so the sum order is fixed and
-// training is deterministic.
+// One wave trains one leaf.  Its training points sit in the wave's LDS
+// slice; the 49 parameters are uniform across the wave.  The 50 per-lane
+// partial sums of an epoch (49 gradients and the squared residual) are
+// reduce-scattered over the wave in a fixed order, so lane l ends with the
+// whole sum of one of them (rs_index(l)); it updates that parameter's Adam
+// moments, and every lane reads the new parameters back from their owners.
+// Training is therefore deterministic.
+
+// Which of the 50 sums lane l holds after wave_reduce_scatter, or -1.  The
+// halvings go by lane bit 5, 4, 2, 3, 1, 0, keeping lists of 25, 13, 7, 4, 2
+// and 1 values (the upper part of an odd list is padded with zero).
+constexpr int rs_index(int l) {
+    const int b0 = l & 1, b1 = (l >> 1) & 1, b2 = (l >> 2) & 1, b3 = (l >> 3) & 1, b4 = (l >> 4) & 1,
+              b5 = (l >> 5) & 1;
+    const int k4 = 4 * b3 + 2 * b1 + b0;
+    if (k4 >= 7) return -1;
+    const int k3 = 7 * b2 + k4;
+    if (k3 >= 13) return -1;
+    const int k2 = 13 * b4 + k3;
+    if (k2 >= 25) return -1;
+    return 25 * b5 + k2;
+}
+
+struct LaneOf {
+    int v[kNP + 1];
+};
+constexpr LaneOf make_lane_of() {
+    LaneOf t{};
+    for (int l = 0; l < kWave; ++l)
+        if (rs_index(l) >= 0) t.v[rs_index(l)] = l;
+    return t;
+}
+constexpr LaneOf kLaneOf = make_lane_of();
+static_assert(kLaneOf.v[0] == 0 && kLaneOf.v[kNP] == 60, "reduce-scatter lane map");
 
 template <int CTRL>
-__device__ __forceinline__ float row_ror(float v) {
+__device__ __forceinline__ float dpp_f(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
-// Sum over the 64 lanes, returned to every lane.
-__device__ __forceinline__ float wave_allsum(float v) {
-    v += row_ror<0x128>(v);   // row_ror:8
-    v += row_ror<0x124>(v);   // row_ror:4
-    v += row_ror<0x122>(v);   // row_ror:2
-    v += row_ror<0x121>(v);   // row_ror:1
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    return v;
+// One halving inside rows of 16 lanes: lanes with bit BIT clear keep the
+// first N_OUT values, the others the rest (zero past N_IN); each lane adds
+// what its partner, read through the DPP pattern CTRL, does not keep.
+template <int N_IN, int N_OUT, int BIT, int CTRL>
+__device__ __forceinline__ void rs_halve(const float* in, float* out, uint32_t lane) {
+    const bool hi = (lane >> BIT) & 1u;
+#pragma unroll
+    for (int k = 0; k < N_OUT; ++k) {
+        const float a = in[k], b = N_OUT + k < N_IN ? in[N_OUT + k] : 0.0f;
+        out[k] = (hi ? b : a) + dpp_f<CTRL>(hi ? a : b);
+    }
+}
+
+// Wave sum of g[0..49] (each lane's partial sums), scattered: returns in lane
+// l the sum of g[rs_index(l)] over the 64 lanes.  v_permlane32_swap and
+// v_permlane16_swap exchange the halves of the wave and of each 32 lanes;
+// DPP row_ror:4, row_ror:8 and two quad permutations do the rest.
+__device__ __forceinline__ float wave_reduce_scatter(const float (&g)[kNP + 1]) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    float a[25], b[13], c[7], d[4], e[2], f[1];
+#pragma unroll
+    for (int j = 0; j < 25; ++j) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(g[j]), __float_as_uint(g[25 + j]), false,
+                                                        false);
+        a[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int k = 0; k < 13; ++k) {
+        const float hi = 13 + k < 25 ? a[13 + k] : 0.0f;
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[k]), __float_as_uint(hi), false, false);
+        b[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    rs_halve<13, 7, 2, 0x124>(b, c, lane);   // row_ror:4
+    rs_halve<7, 4, 3, 0x128>(c, d, lane);    // row_ror:8
+    rs_halve<4, 2, 1, 0x4E>(d, e, lane);     // quad_perm [2,3,0,1]
+    rs_halve<2, 1, 0, 0xB1>(e, f, lane);     // quad_perm [1,0,3,2]
+    return f[0];
 }
 
 // Loss gradient of the leaf model over points (u[j], t[j]), j < m: lane l
-// takes points l, l + 64, ... in order.  g[0..48] are the parameter
-// gradients of mean (y - t)^2 and g[49] the summed squared residual, all
-// complete in every lane.
-__device__ __forceinline__ void wave_grad(const float (&p)[kNP], const float* u, const float* t, uint32_t m,
-                                          float (&g)[kNP + 1]) {
+// takes points l, l + 64, ... in order.  The per-lane partial sums are the
+// gradients of mean (y - t)^2 with respect to the 49 parameters and, as
+// value 49, the summed squared residual; the return value is lane l's
+// reduce-scattered sum (of value rs_index(l)).
+__device__ __forceinline__ float wave_grad(const float (&p)[kNP], const float* u, const float* t, uint32_t m) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const float scale = m ? 2.0f / (float)m : 0.0f;
+    float g[kNP + 1];
 #pragma unroll
     for (int k = 0; k <= kNP; ++k) g[k] = 0.0f;
 #pragma unroll 1
@@ -174,8 +232,7 @@ __device__ __forceinline__ void wave_grad(const float (&p)[kNP], const float* u,
             g[16 + q] += dh;
         }
     }
-#pragma unroll
-    for (int k = 0; k <= kNP; ++k) g[k] = wave_allsum(g[k]);
+    return wave_reduce_scatter(g);
 }
 
 __device__ __forceinline__ uint32_t lower_bound_in(const uint32_t* K, uint32_t lo, uint32_t hi, uint32_t x) {
@@ -203,8 +260,9 @@ struct TrainCfg {
 
 constexpr int kTrainWaves = 2;
 
+// Dynamic LDS: 2 * tc.max_points floats per wave.
 __global__ void __launch_bounds__(kTrainWaves * kWave) k_rmi_train(Pair2 P, TrainCfg tc) {
-    __shared__ float pts[kTrainWaves][2][BITS_RMI_MAX_POINTS];
+    extern __shared__ float pts[];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wv = threadIdx.x / kWave;
     const int a = blockIdx.y;
@@ -225,8 +283,8 @@ __global__ void __launch_bounds__(kTrainWaves * kWave) k_rmi_train(Pair2 P, Trai
 
     // training point j: the key at rank rlo + floor(j * cnt / m), target its
     // lower-bound rank normalised to the leaf
-    float* u = pts[wv][0];
-    float* t = pts[wv][1];
+    float* u = pts + (size_t)wv * 2 * tc.max_points;
+    float* t = u + tc.max_points;
     for (uint32_t j = lane; j < m; j += kWave) {
         const uint32_t i = rlo + (uint32_t)(((uint64_t)j * cnt) / m);
         const uint32_t x = K[i];
@@ -266,32 +324,28 @@ __global__ void __launch_bounds__(kTrainWaves * kWave) k_rmi_train(Pair2 P, Trai
         p[48] = tv[0];
     }
 
-    // Full-batch Adam; lane k < 49 updates parameter k, then every lane
-    // reads the new parameters back from their owners.
+    // Full-batch Adam; lane l updates parameter rs_index(l) (when < 49), then
+    // every lane reads the new parameters back from their owners.
+    const int mine = rs_index((int)lane);
+    const bool owner = mine >= 0 && mine < kNP;
     float own = 0.0f;
 #pragma unroll
     for (int j = 0; j < kNP; ++j)
-        if (lane == (uint32_t)j) own = p[j];
+        if (mine == j) own = p[j];
     float mom = 0.0f, vel = 0.0f, b1t = 1.0f, b2t = 1.0f;
-    float g[kNP + 1];
     for (uint32_t e = 0; e < tc.epochs; ++e) {
-        wave_grad(p, u, t, m, g);
-        float gk = 0.0f;
-#pragma unroll
-        for (int j = 0; j < kNP; ++j)
-            if (lane == (uint32_t)j) gk = g[j];
+        const float gk = wave_grad(p, u, t, m);
         mom = tc.beta1 * mom + (1.0f - tc.beta1) * gk;
         vel = tc.beta2 * vel + (1.0f - tc.beta2) * gk * gk;
         b1t *= tc.beta1;
         b2t *= tc.beta2;
         const float mh = mom / (1.0f - b1t);
         const float vh = vel / (1.0f - b2t);
-        if (lane < (uint32_t)kNP) own -= tc.lr * mh / (sqrtf(vh) + 1e-8f);
+        if (owner) own -= tc.lr * mh / (sqrtf(vh) + 1e-8f);
 #pragma unroll
-        for (int j = 0; j < kNP; ++j) p[j] = bcast(own, j);
+        for (int j = 0; j < kNP; ++j) p[j] = bcast(own, kLaneOf.v[j]);
     }
-    wave_grad(p, u, t, m, g);
-    const float last_loss = g[kNP] / (float)m;
+    const float last_loss = bcast(wave_grad(p, u, t, m), kLaneOf.v[kNP]) / (float)m;
 
     // The stored model: w1, b1, w2 rounded to binary16, b2 kept in fp32.
     float q[kNP];
@@ -347,18 +401,13 @@ __global__ void __launch_bounds__(kWave) k_leaf_grad(const float* u_in, const fl
         pts[1][j] = t_in[j];
     }
     __syncthreads();
-    float p[kNP], g[kNP + 1];
+    float p[kNP];
 #pragma unroll
     for (int j = 0; j < kNP; ++j) p[j] = params[j];
-    wave_grad(p, pts[0], pts[1], m, g);
-    if (lane < (uint32_t)kNP) {
-        float gk = 0.0f;
-#pragma unroll
-        for (int j = 0; j < kNP; ++j)
-            if (lane == (uint32_t)j) gk = g[j];
-        grad[lane] = gk;
-    }
-    if (lane == 0) *loss = m ? g[kNP] / (float)m : 0.0f;
+    const float gs = wave_grad(p, pts[0], pts[1], m);
+    const int mine = rs_index((int)lane);
+    if (mine >= 0 && mine < kNP) grad[mine] = gs;
+    if (mine == kNP) *loss = m ? gs / (float)m : 0.0f;
 }
 
 }  // namespace
@@ -391,7 +440,8 @@ int launch_rmi_build2(const uint32_t* keys0, const uint32_t* keys1, uint64_t n, 
     if (gb < 1) gb = 1;
     hipLaunchKernelGGL(k_rmi_bounds, dim3(gb, 2), dim3(256), 0, s, P, n);
     TrainCfg tc{tr.epochs, tr.max_points, tr.lr, tr.beta1, tr.beta2};
-    hipLaunchKernelGGL(k_rmi_train, dim3(BITS_RMI_LEAVES / kTrainWaves, 2), dim3(kTrainWaves * kWave), 0, s, P, tc);
+    const size_t lds = (size_t)kTrainWaves * 2 * tc.max_points * sizeof(float);
+    hipLaunchKernelGGL(k_rmi_train, dim3(BITS_RMI_LEAVES / kTrainWaves, 2), dim3(kTrainWaves * kWave), lds, s, P, tc);
     BITS_CHECK_HIP(hipGetLastError());
     return BITS_OK;
 }
