@@ -52,6 +52,9 @@ typedef enum bits_status {
 #define BITS_FLAG_CHROM    0x2u   /* interval outside its chromosome */
 #define BITS_FLAG_ENUM     0x4u   /* enumeration: a query's scan found fewer pairs than its
                                      count, or the pair buffer was too small */
+#define BITS_FLAG_SORT     0x8u   /* radix sort: a tile gave up waiting for the digit counts
+                                     of the tiles before it (never expected; the sorted
+                                     output is then invalid) */
 
 #define BITS_MAX_CHROM   256u     /* chromosomes per genome for projection / Monte-Carlo */
 #define BITS_MC_BIN_MAX_BATCH 1024u /* shuffles per pass of bits_mc_binned */
@@ -205,7 +208,8 @@ int bits_sort_ref_workspace(uint64_t n, size_t *bytes);
  * sorted ascending by an on-device LSD radix sort (8-bit digits, digits
  * constant over the whole input skipped), the Eytzinger top tree of each is
  * built, and if ref->learned the learned CDF index is trained on the device
- * and its per-leaf error windows measured.  Clears the status word.
+ * and its per-leaf error windows measured.  Clears the status word (then
+ * BITS_FLAG_SORT reports a sort that could not complete).
  *   d_b_start, d_b_end  device, ref->n each, unsorted (not modified)
  *   d_ws, ws_bytes      device workspace >= bits_sort_ref_workspace(n)
  *   train               host, NULL for defaults (ignored if not learned)

@@ -211,8 +211,9 @@ int bits_sort_refs_workspace(const uint64_t* n, uint32_t n_ref, size_t* bytes) {
     return BITS_OK;
 }
 
+// Builds the rest of a reference index from its sorted arrays; the status
+// block was cleared before the sort.
 static int finish_ref(const bits_ref* r, const bits_train& tr, void* ws, hipStream_t s) {
-    BITS_CHECK_HIP(launch_fill_u32(r->status, kStatusBytes / 4, 0u, s));
     if (r->n) {
         // keys past n up to the end of the last 128-byte line read as +inf
         const uint64_t pad = ((r->n + 31) & ~31ull) - r->n;
@@ -245,10 +246,12 @@ int bits_sort_ref(const uint32_t* d_b_start, const uint32_t* d_b_end, const bits
     bits_sort_ref_workspace(ref->n, &need);
     if (ref->n && ws_bytes < need) return BITS_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
+    BITS_CHECK_HIP(launch_fill_u32(ref->status, kStatusBytes / 4, 0u, s));
     if (ref->n) {
         SortSeg segs[2] = {{d_b_start, ref->bs, ref->n}, {d_b_end, ref->be, ref->n}};
         const int rc = launch_sort(segs, 2, d_ws, ws_bytes, s);
         if (rc != BITS_OK) return rc;
+        BITS_CHECK_HIP(launch_sort_report(d_ws, ref->status, s));
     }
     return finish_ref(ref, train_defaults(train), d_ws, s);
 }
@@ -271,8 +274,10 @@ int bits_sort_refs(const uint32_t* const* d_b_start, const uint32_t* const* d_b_
     bits_sort_refs_workspace(ns.data(), n_ref, &need);
     if (ws_bytes < need) return BITS_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
+    for (uint32_t j = 0; j < n_ref; ++j) BITS_CHECK_HIP(launch_fill_u32(refs[j].status, kStatusBytes / 4, 0u, s));
     int rc = launch_sort(segs.data(), (uint32_t)segs.size(), d_ws, ws_bytes, s);
     if (rc != BITS_OK) return rc;
+    for (uint32_t j = 0; j < n_ref; ++j) BITS_CHECK_HIP(launch_sort_report(d_ws, refs[j].status, s));
     const bits_train tr = train_defaults(train);
     for (uint32_t j = 0; j < n_ref; ++j) {
         rc = finish_ref(&refs[j], tr, d_ws, s);
@@ -838,6 +843,7 @@ int bits_mc_resort(const uint32_t* d_a_start, const uint32_t* d_a_end, uint64_t 
             }
             const int rc = launch_sort(segs.data(), 2 * rounds, sort_ws, sort_bytes, s);
             if (rc != BITS_OK) return rc;
+            BITS_CHECK_HIP(launch_sort_report(sort_ws, status, s));
             BITS_CHECK_HIP(launch_count_rounds(S_out, E_out, nb, rounds, d_a_start, d_a_end, na, out, status, s));
             return BITS_OK;
         };

@@ -293,6 +293,10 @@ struct SortSeg {
 };
 size_t sort_workspace_bytes(const uint64_t* n, uint32_t nseg, const uint32_t* vmode = nullptr);
 int launch_sort(const SortSeg* segs, uint32_t nseg, void* ws, size_t ws_bytes, hipStream_t s);
+// After launch_sort, before anything else writes ws: ORs BITS_FLAG_SORT into
+// *status if a tile's look-back walk gave up (never expected; the sorted
+// output is then invalid).
+hipError_t launch_sort_report(const void* ws, uint32_t* status, hipStream_t s);
 hipError_t launch_build_tree(const uint32_t* keys, uint64_t n, uint32_t depth, uint32_t* tree, hipStream_t s);
 // Line heads of a sorted array: H[j] = keys[32 j] for j < ceil(n / 32), then
 // 0xFFFFFFFF up to heads_len(n) entries.

@@ -4,11 +4,16 @@
 // Segmented: every segment (e.g. B_S and B_E of one or many references) is
 // sorted independently in the same launches, keys only or with one uint32
 // value per key carried along (explicit, or the implicit 0..n-1 input order;
-// the sort is stable, so equal keys keep their input order).  Four passes of
-// 8-bit digits, reduce-then-scan per pass:
-//   tile histogram -> per (segment, digit) scan over tiles -> stable scatter.
-// A digit that is constant over every segment is skipped (decided on the
-// device, so the sort never waits for the host).  Inputs are never written.
+// the sort is stable, so equal keys keep their input order).  One read of
+// the input counts all four 8-bit digits of every segment; then each pass is
+// a single kernel over tiles of 16384 keys taken in order from a counter:
+// the tile ranks its keys by digit, publishes its digit counts, adds up the
+// counts of the tiles before it in its segment by decoupled look-back (the
+// nearest tile that has published its inclusive prefix ends the walk), and
+// writes its keys out in digit runs.  Every key is read once and written
+// once per pass.  A digit that is constant over every segment is skipped
+// (decided on the device, so the sort never waits for the host).  Inputs
+// are never written.
 #include <string.h>
 
 #include <vector>
@@ -19,11 +24,23 @@ namespace bits {
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;                  // histogram, scan and copy kernels
 constexpr int kWaves = kThreads / kWave;
+constexpr int kSweepThreads = 1024;            // one pass of the sort
+constexpr int kSweepWaves = kSweepThreads / kWave;
 constexpr uint32_t kPerWave = 1024;            // keys per wave per tile
-constexpr uint32_t kTile = kPerWave * kWaves;  // 4096 keys per tile
+constexpr uint32_t kTile = kPerWave * kSweepWaves;  // 16384 keys per tile
 constexpr int kRounds = kPerWave / kWave;      // 16 rounds of 64 keys
+// Look-back words, one per (tile, digit): bits 0-31 the count, bits 32-39
+// the pass (1 + p; 0 = not yet published in this call), bit 40 set once the
+// count is the inclusive prefix over the segment's tiles up to this one
+// (else it is the tile's own count).
+constexpr uint64_t kLbPrefix = 1ull << 40;
+// Polls of a predecessor's word before giving up (the walk cannot deadlock:
+// tiles are taken in order, so every tile waited on is held by a running
+// workgroup; the bound only turns a fault into BITS_FLAG_SORT, not a hang).
+constexpr uint32_t kLbSpinLimit = 1u << 22;
+constexpr int kLbBatch = 8;   // predecessor words loaded at once
 
 struct SegDesc {
     const uint32_t* in;
@@ -44,7 +61,9 @@ struct SortPlan {
     uint32_t src[4];   // 0 = input, 1 = ping, 2 = output
     uint32_t dst[4];
     uint32_t n_active;
-    uint32_t pad[3];
+    uint32_t next_tile[4];   // tile counter of each pass
+    uint32_t error;          // nonzero: a look-back walk gave up (output invalid)
+    uint32_t pad[2];
 };
 
 constexpr int kDescChunk = 48;   // 3 KB of kernel arguments
@@ -185,64 +204,55 @@ __global__ void k_plan(SortPlan* plan) {
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_tile_hist(const SegDesc* __restrict__ descs, uint32_t nseg,
-                                                        const SortPlan* __restrict__ plan, int p,
-                                                        uint32_t ntiles, uint32_t* __restrict__ H) {
-    if (!plan->active[p]) return;
-    __shared__ uint32_t h[256];
-    const uint32_t t = blockIdx.x;
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t s = seg_of_tile(descs, nseg, t);
-    const SegDesc d = descs[s];
-    const uint32_t begin = (t - d.tile0) * kTile;
-    const uint32_t cnt = min(kTile, d.n - begin);
-    const uint32_t* src = buf_ro(d, plan->src[p]) + begin;
-    const uint32_t shift = 8u * p;
-    for (uint32_t k = threadIdx.x; k < cnt; k += kThreads) atomicAdd(&h[(src[k] >> shift) & 255u], 1u);
-    __syncthreads();
-    H[(size_t)threadIdx.x * ntiles + t] = h[threadIdx.x];
+// The look-back word of (tile, digit).
+__device__ __forceinline__ unsigned long long* lb_word(unsigned long long* lb, uint32_t ntiles, uint32_t tile,
+                                                      uint32_t dg) {
+    return lb + (size_t)tile * 256 + dg;
 }
 
-// Block (s, digit): exclusive scan of H[digit][tiles of s] in place.
-__global__ void __launch_bounds__(kThreads) k_tile_scan(const SegDesc* __restrict__ descs,
-                                                        const SortPlan* __restrict__ plan, int p,
-                                                        uint32_t ntiles, uint32_t* __restrict__ H) {
-    if (!plan->active[p]) return;
-    __shared__ uint32_t tmp[kWaves];
-    const uint32_t s = blockIdx.x >> 8, dg = blockIdx.x & 255u;
-    const SegDesc d = descs[s];
-    const uint32_t nt = (d.n + kTile - 1) / kTile;
-    uint32_t* row = H + (size_t)dg * ntiles + d.tile0;
-    const uint32_t per = (nt + kThreads - 1) / kThreads;
-    const uint32_t b = threadIdx.x * per, e = min(nt, b + per);
-    uint32_t sum = 0;
-    for (uint32_t k = b; k < e; ++k) sum += row[k];
-    uint32_t run = block_excl_scan(sum, tmp, nullptr);
-    for (uint32_t k = b; k < e; ++k) {
-        const uint32_t v = row[k];
-        row[k] = run;
-        run += v;
+template <int WAVES>
+__device__ __forceinline__ uint32_t block_excl_scan_n(uint32_t v, uint32_t* tmp) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
     }
+    if (lane == kWave - 1) tmp[w] = x;
+    __syncthreads();
+    uint32_t pre = 0;
+#pragma unroll
+    for (int k = 0; k < WAVES; ++k)
+        if (k < w) pre += tmp[k];
+    __syncthreads();
+    return pre + x - v;
 }
 
-// Stable scatter of one tile.  Wave w ranks keys [w*1024, (w+1)*1024) of the
-// tile in 16 rounds; within a round, lanes holding the same digit are found
-// with 8 ballots and ranked by lane order.  The tile is then sorted by digit
-// in LDS and written out in digit runs (coalesced).
+// One pass of the sort over one tile (taken from the pass's counter).  Wave
+// w ranks keys [w*1024, (w+1)*1024) of the tile in 16 rounds; within a
+// round, lanes holding the same digit are found with 8 ballots (each folded
+// into the lane's peer mask by one v_bitop3 per half) and ranked by lane
+// order.  The tile's digit counts are published, the exclusive prefix
+// over the segment's earlier tiles is gathered by look-back (one thread per
+// digit), and the tile, sorted by digit in LDS, is written out in digit runs.
 template <bool VALS>
-__global__ void __launch_bounds__(kThreads) k_scatter(const SegDesc* __restrict__ descs, uint32_t nseg,
-                                                      const SortPlan* __restrict__ plan, int p, uint32_t ntiles,
-                                                      const uint32_t* __restrict__ H,
-                                                      const uint32_t* __restrict__ seg_pre) {
+__global__ void __launch_bounds__(kSweepThreads) k_onesweep(const SegDesc* __restrict__ descs, uint32_t nseg,
+                                                            SortPlan* plan, int p,
+                                                            unsigned long long* __restrict__ lb, uint32_t ntiles,
+                                                            const uint32_t* __restrict__ seg_pre) {
     if (!plan->active[p]) return;
     __shared__ uint32_t keys_lds[kTile];
     __shared__ uint32_t vals_lds[VALS ? kTile : 1];
-    __shared__ uint32_t wcnt[kWaves][256];
+    __shared__ uint32_t wcnt[kSweepWaves][256];
     __shared__ uint32_t dstart[256];
     __shared__ uint32_t goff[256];
-    __shared__ uint32_t tmp[kWaves];
-    const uint32_t t = blockIdx.x;
+    __shared__ uint32_t tmp[kSweepWaves];
+    __shared__ uint32_t tile_sh;
+    if (threadIdx.x == 0) tile_sh = atomicAdd(&plan->next_tile[p], 1u);
+    for (int k = threadIdx.x; k < kSweepWaves * 256; k += kSweepThreads) (&wcnt[0][0])[k] = 0;
+    __syncthreads();
+    const uint32_t t = tile_sh;
     const uint32_t s = seg_of_tile(descs, nseg, t);
     const SegDesc d = descs[s];
     const uint32_t begin = (t - d.tile0) * kTile;
@@ -258,9 +268,6 @@ __global__ void __launch_bounds__(kThreads) k_scatter(const SegDesc* __restrict_
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-    for (int k = threadIdx.x; k < kWaves * 256; k += kThreads) (&wcnt[0][0])[k] = 0;
-    __syncthreads();
-
     uint32_t key[kRounds], rank[kRounds];
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
@@ -272,13 +279,17 @@ __global__ void __launch_bounds__(kThreads) k_scatter(const SegDesc* __restrict_
         const uint32_t idx = (uint32_t)w * kPerWave + (uint32_t)r * kWave + lane;
         const bool valid = idx < cnt;
         const uint32_t dg = (key[r] >> shift) & 255u;
-        uint64_t peers = __ballot(valid);
+        const uint64_t pv = __ballot(valid);
+        uint32_t plo = (uint32_t)pv, phi = (uint32_t)(pv >> 32);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            const bool bit = (dg >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
+            const uint32_t sb = 0u - ((dg >> b) & 1u);   // all ones where the bit is set
+            const uint64_t m = __ballot(sb != 0u);
+            // peers &= bit ? m : ~m, i.e. peers & ~(m ^ sb): one v_bitop3 per half
+            plo = __builtin_amdgcn_bitop3_b32(plo, (uint32_t)m, sb, 0x90);
+            phi = __builtin_amdgcn_bitop3_b32(phi, (uint32_t)(m >> 32), sb, 0x90);
         }
+        const uint64_t peers = ((uint64_t)phi << 32) | plo;
         const uint32_t before = (uint32_t)__popcll(peers & lt_mask);
         uint32_t old = 0;
         if (valid) old = wcnt[w][dg];
@@ -287,36 +298,81 @@ __global__ void __launch_bounds__(kThreads) k_scatter(const SegDesc* __restrict_
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    {
-        const uint32_t dg = threadIdx.x;
-        uint32_t tot = 0;
+    // per digit: wave offsets within the tile, the tile's count, published at once
+    uint32_t tot = 0;
+    const uint32_t dg = threadIdx.x;
+    const unsigned long long tag = (unsigned long long)(p + 1) << 32;
+    if (dg < 256) {
 #pragma unroll
-        for (int k = 0; k < kWaves; ++k) {
+        for (int k = 0; k < kSweepWaves; ++k) {
             const uint32_t c = wcnt[k][dg];
             wcnt[k][dg] = tot;
             tot += c;
         }
-        dstart[dg] = block_excl_scan(tot, tmp, nullptr);
-        goff[dg] = seg_pre[((size_t)s * 4 + p) * 256 + dg] + H[(size_t)dg * ntiles + t];
+        __hip_atomic_store(lb_word(lb, ntiles, t, dg), (d.tile0 == t ? kLbPrefix : 0ull) | tag | tot, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
+    const uint32_t ds = block_excl_scan_n<kSweepWaves>(dg < 256 ? tot : 0u, tmp);
+    if (dg < 256) dstart[dg] = ds;
     __syncthreads();
+    // the tile sorted by digit in LDS (needs only tile-local offsets)
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         const uint32_t idx = (uint32_t)w * kPerWave + (uint32_t)r * kWave + lane;
         if (idx < cnt) {
-            const uint32_t dg = (key[r] >> shift) & 255u;
-            const uint32_t at = dstart[dg] + wcnt[w][dg] + rank[r];
+            const uint32_t kd = (key[r] >> shift) & 255u;
+            const uint32_t at = dstart[kd] + wcnt[w][kd] + rank[r];
             keys_lds[at] = key[r];
             if constexpr (VALS) {
                 if (vals) vals_lds[at] = iota ? begin + idx : vsrc[idx];
             }
         }
     }
+    if (dg < 256) {
+        // look-back over the segment's earlier tiles, kLbBatch words loaded at
+        // once (independent loads), then taken nearest first: a word not yet
+        // published is polled until it is; the walk ends at an inclusive prefix
+        uint32_t excl = 0;
+        if (t != d.tile0) {
+            uint32_t tp = t - 1;
+            uint32_t spins = 0;
+            bool done = false;
+            while (!done) {
+                unsigned long long v[kLbBatch];
+#pragma unroll
+                for (int k = 0; k < kLbBatch; ++k) {
+                    const uint32_t tk = tp >= d.tile0 + (uint32_t)k ? tp - (uint32_t)k : d.tile0;
+                    v[k] = __hip_atomic_load(lb_word(lb, ntiles, tk, dg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+#pragma unroll
+                for (int k = 0; k < kLbBatch; ++k) {
+                    if (done) break;
+                    const uint32_t tk = tp - (uint32_t)k;
+                    while ((v[k] & (0xFFull << 32)) != tag) {
+                        if (++spins > kLbSpinLimit) {
+                            atomicOr(&plan->error, 1u);
+                            v[k] = kLbPrefix | tag;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                        v[k] = __hip_atomic_load(lb_word(lb, ntiles, tk, dg), __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    excl += (uint32_t)v[k];
+                    done = (v[k] & kLbPrefix) || tk == d.tile0;
+                }
+                tp -= kLbBatch;
+            }
+            __hip_atomic_store(lb_word(lb, ntiles, t, dg), kLbPrefix | tag | (excl + tot), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        goff[dg] = seg_pre[((size_t)s * 4 + p) * 256 + dg] + excl;
+    }
     __syncthreads();
-    for (uint32_t k = threadIdx.x; k < cnt; k += kThreads) {
+    for (uint32_t k = threadIdx.x; k < cnt; k += kSweepThreads) {
         const uint32_t v = keys_lds[k];
-        const uint32_t dg = (v >> shift) & 255u;
-        const uint32_t at = goff[dg] + (k - dstart[dg]);
+        const uint32_t kd = (v >> shift) & 255u;
+        const uint32_t at = goff[kd] + (k - dstart[kd]);
         dst[at] = v;
         if constexpr (VALS) {
             if (vals) vdst[at] = vals_lds[k];
@@ -364,7 +420,7 @@ __global__ void k_build_heads(const uint32_t* __restrict__ keys, uint64_t n, uin
 }
 
 struct WsLayout {
-    size_t descs, plan, seg_hist, seg_pre, H, ping, vping, total;
+    size_t descs, plan, seg_hist, seg_pre, lb, ping, vping, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -378,11 +434,11 @@ static WsLayout ws_layout(const uint64_t* n, uint32_t nseg, const uint32_t* vmod
     }
     WsLayout L;
     size_t o = 0;
+    L.plan = o; o = align256(o + sizeof(SortPlan));   // first: launch_sort_report finds it at 0
     L.descs = o; o = align256(o + sizeof(SegDesc) * nseg);
-    L.plan = o; o = align256(o + sizeof(SortPlan));
     L.seg_hist = o; o = align256(o + (size_t)nseg * 1024 * 4);
     L.seg_pre = o; o = align256(o + (size_t)nseg * 1024 * 4);
-    L.H = o; o = align256(o + (size_t)ntiles * 256 * 4);
+    L.lb = o; o = align256(o + (size_t)ntiles * 256 * 8);
     L.ping = o; o = align256(o + (size_t)nkeys * 4);
     L.vping = o; o = align256(o + (size_t)nvals * 4);
     L.total = o;
@@ -413,7 +469,7 @@ int launch_sort(const SortSeg* segs, uint32_t nseg, void* ws, size_t ws_bytes, h
     SortPlan* plan = (SortPlan*)(base + L.plan);
     uint32_t* seg_hist = (uint32_t*)(base + L.seg_hist);
     uint32_t* seg_pre = (uint32_t*)(base + L.seg_pre);
-    uint32_t* H = (uint32_t*)(base + L.H);
+    unsigned long long* lb = (unsigned long long*)(base + L.lb);
     uint32_t* ping = (uint32_t*)(base + L.ping);
     uint32_t* vping = (uint32_t*)(base + L.vping);
 
@@ -452,23 +508,33 @@ int launch_sort(const SortSeg* segs, uint32_t nseg, void* ws, size_t ws_bytes, h
         return BITS_OK;
     }
 
+    BITS_CHECK_HIP(launch_fill_u64(lb, (uint64_t)ntiles * 256, 0ull, s));
     const uint32_t hg = ntiles < 2048u ? ntiles : 2048u;
     hipLaunchKernelGGL(k_hist_all, dim3(hg), dim3(kThreads), 0, s, descs, nseg, ntiles, seg_hist);
     hipLaunchKernelGGL(k_seg_scan, dim3(nseg * 4), dim3(kThreads), 0, s, seg_hist, seg_pre, plan);
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, s, plan);
     for (int p = 0; p < 4; ++p) {
-        hipLaunchKernelGGL(k_tile_hist, dim3(ntiles), dim3(kThreads), 0, s, descs, nseg, plan, p, ntiles, H);
-        hipLaunchKernelGGL(k_tile_scan, dim3(nseg * 256), dim3(kThreads), 0, s, descs, plan, p, ntiles, H);
         if (any_vals)
-            hipLaunchKernelGGL(k_scatter<true>, dim3(ntiles), dim3(kThreads), 0, s, descs, nseg, plan, p, ntiles, H,
-                               seg_pre);
+            hipLaunchKernelGGL(k_onesweep<true>, dim3(ntiles), dim3(kSweepThreads), 0, s, descs, nseg, plan, p, lb,
+                               ntiles, seg_pre);
         else
-            hipLaunchKernelGGL(k_scatter<false>, dim3(ntiles), dim3(kThreads), 0, s, descs, nseg, plan, p, ntiles, H,
-                               seg_pre);
+            hipLaunchKernelGGL(k_onesweep<false>, dim3(ntiles), dim3(kSweepThreads), 0, s, descs, nseg, plan, p, lb,
+                               ntiles, seg_pre);
     }
     hipLaunchKernelGGL(k_copy_if_idle, dim3(ntiles), dim3(kThreads), 0, s, descs, nseg, plan);
     BITS_CHECK_HIP(hipGetLastError());
     return BITS_OK;
+}
+
+// Ors BITS_FLAG_SORT into *status if the last sort in ws gave up a look-back.
+__global__ void k_sort_report(const SortPlan* plan, uint32_t* status) {
+    if (threadIdx.x == 0 && plan->error) atomicOr(status, BITS_FLAG_SORT);
+}
+
+hipError_t launch_sort_report(const void* ws, uint32_t* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_sort_report, dim3(1), dim3(64), 0, s,
+                       reinterpret_cast<const SortPlan*>(ws), status);
+    return hipGetLastError();
 }
 
 hipError_t launch_build_tree(const uint32_t* keys, uint64_t n, uint32_t depth, uint32_t* tree, hipStream_t s) {
