@@ -44,6 +44,7 @@ N_ENUM = 10_000_000   # A-intervals enumerated against the full B (outside the t
 MC_SEED = 7
 MC_BATCH = 1000       # shuffles per pass of the binned Monte-Carlo path (8.2 GB workspace at 1e6 queries)
 TRAIN_EPOCHS = 80
+TRAIN_POINTS = 128    # training points per leaf (the windows are as tight as with 256-2048; see the sweep)
 # Algorithmic HBM bytes per placement (one shuffled A-interval) of the binned Monte-Carlo kernels:
 #   k_bin_place   reads the query's 8-byte {index, length} entry, writes its 8-byte {start, end} record;
 #   k_bin_search  reads the record back (8 bytes); each region also stages its slices of B_S and B_E
@@ -404,7 +405,7 @@ def main():
                              torch.empty(1, dtype=torch.uint64, device=dev),
                              torch.empty(1, dtype=torch.uint64, device=dev))
     mc_out = mc_result()
-    train = {"epochs": args.epochs}
+    train = {"epochs": args.epochs, "max_points": TRAIN_POINTS}
 
     # launch shapes from the autotuner (outside the timed region)
     a_s, a_e = bits.bits_project(lengths, *dA)
@@ -489,7 +490,7 @@ def main():
         rec.update({"ms": t, "aps": N_A / (t / 1e3)})
         gain[name] = rec
     count_path("trained", ref, lp_learned)
-    ref_init = bits.bits_sort_ref(b_s, b_e, learned=True, train={"epochs": 0})
+    ref_init = bits.bits_sort_ref(b_s, b_e, learned=True, train={"epochs": 0, "max_points": TRAIN_POINTS})
     count_path("init_only", ref_init, lp_learned)
     del ref_init
     count_path("tiered_no_model", ref, lp_tiered)
@@ -622,6 +623,7 @@ def main():
         "config": {"workload": "learned index at scale: B=5e7 clustered, A=5e7 uniform, MC 1000 x 1e6 "
                                "(24-chromosome genome)",
                    "n_b": N_B, "n_a": N_A, "mc_queries": N_MC, "mc_shuffles": N_SHUF, "train_epochs": args.epochs,
+                   "train_points": TRAIN_POINTS,
                    "launch_learned": lp_learned, "launch_plain": lp_plain, "launch_tiered": lp_tiered,
                    "mc": {"path": "binned by genome region", "batch": MC_BATCH, "observed_launch": lp_mc}},
         "library": library_info(bits),

@@ -21,10 +21,11 @@ constexpr int kWaves = kThreads / kWave;
 constexpr int kSumBlocks = 512;
 constexpr int kNP = BITS_RMI_PARAMS;   // 49
 
-struct Sums {   // exact partial sums of one block
-    unsigned long long sx;
-    unsigned long long sxx_lo, sxx_hi;
-    unsigned long long sxi_lo, sxi_hi;
+// Exact partial sums of one block, each a plain uint64 that cannot wrap for
+// n < 2^32: sum x; the low and high 32-bit halves of x^2 and of x*i (i =
+// rank), summed separately (each half < 2^32, so any n < 2^32 of them fit).
+struct Sums {
+    unsigned long long sx, xx_lo, xx_hi, xi_lo, xi_hi;
     unsigned long long pad[3];
 };
 
@@ -35,58 +36,64 @@ struct Pair2 {
     Sums* sums[2];
 };
 
-__device__ __forceinline__ void add128(unsigned long long& lo, unsigned long long& hi, unsigned __int128 v) {
-    const unsigned __int128 cur = ((unsigned __int128)hi << 64) | lo;
-    const unsigned __int128 r = cur + v;
-    lo = (unsigned long long)r;
-    hi = (unsigned long long)(r >> 64);
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
 }
 
-// Exact sums over the keys: sum x, sum x^2, sum x*i (i = rank).
+// Exact sums over the keys: sum x, sum x^2, sum x*i (i = rank), as split
+// halves (Sums); one read of the sorted keys.
 __global__ void __launch_bounds__(kThreads) k_rmi_sums(Pair2 P, uint64_t n) {
     const int a = blockIdx.y;
     const uint32_t* K = P.keys[a];
-    unsigned long long sx = 0;
-    unsigned __int128 sxx = 0, sxi = 0;
+    unsigned long long v[5] = {0ull, 0ull, 0ull, 0ull, 0ull};
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t x = K[i];
-        sx += x;
-        sxx += (unsigned __int128)(x * x);
-        sxi += (unsigned __int128)x * i;
+        const uint32_t x = K[i];
+        const uint64_t xx = (uint64_t)x * x, xi = (uint64_t)x * (uint32_t)i;   // i < n < 2^32
+        v[0] += x;
+        v[1] += (uint32_t)xx;
+        v[2] += (uint32_t)(xx >> 32);
+        v[3] += (uint32_t)xi;
+        v[4] += (uint32_t)(xi >> 32);
     }
-    __shared__ unsigned long long r[5][kThreads];
-    r[0][threadIdx.x] = sx;
-    r[1][threadIdx.x] = (unsigned long long)sxx;
-    r[2][threadIdx.x] = (unsigned long long)(sxx >> 64);
-    r[3][threadIdx.x] = (unsigned long long)sxi;
-    r[4][threadIdx.x] = (unsigned long long)(sxi >> 64);
+    __shared__ unsigned long long r[kWaves][5];
+    const uint32_t lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const unsigned long long t = wave_sum_u64(v[k]);
+        if (lane == 0) r[w][k] = t;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        Sums S{};
-        for (int t = 0; t < kThreads; ++t) {
-            S.sx += r[0][t];
-            add128(S.sxx_lo, S.sxx_hi, ((unsigned __int128)r[2][t] << 64) | r[1][t]);
-            add128(S.sxi_lo, S.sxi_hi, ((unsigned __int128)r[4][t] << 64) | r[3][t]);
-        }
-        P.sums[a][blockIdx.x] = S;
+    if (threadIdx.x < 5) {
+        unsigned long long t = 0;
+        for (int k = 0; k < kWaves; ++k) t += r[k][threadIdx.x];
+        (&P.sums[a][blockIdx.x].sx)[threadIdx.x] = t;
     }
 }
 
 // Root line from the exact sums; routing slope/intercept pre-scaled by 4096/n.
-__global__ void k_rmi_root(Pair2 P, uint64_t n, uint32_t nblocks) {
-    const int a = threadIdx.x;
-    if (a >= 2) return;
-    unsigned long long sx = 0, xx_lo = 0, xx_hi = 0, xi_lo = 0, xi_hi = 0;
-    for (uint32_t b = 0; b < nblocks; ++b) {
-        const Sums S = P.sums[a][b];
-        sx += S.sx;
-        add128(xx_lo, xx_hi, ((unsigned __int128)S.sxx_hi << 64) | S.sxx_lo);
-        add128(xi_lo, xi_hi, ((unsigned __int128)S.sxi_hi << 64) | S.sxi_lo);
+// One wave per array (blockDim 128): the block partials are summed per lane,
+// then over the wave, then combined exactly in 128 bits.
+__global__ void __launch_bounds__(2 * kWave) k_rmi_root(Pair2 P, uint64_t n, uint32_t nblocks) {
+    const int a = threadIdx.x / kWave;
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    unsigned long long v[5] = {0ull, 0ull, 0ull, 0ull, 0ull};
+    for (uint32_t b = lane; b < nblocks; b += kWave) {
+        const Sums& S = P.sums[a][b];
+        v[0] += S.sx;
+        v[1] += S.xx_lo;
+        v[2] += S.xx_hi;
+        v[3] += S.xi_lo;
+        v[4] += S.xi_hi;
     }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[k] = wave_sum_u64(v[k]);
+    if (lane != 0) return;
     const __int128 N = (__int128)n;
-    const __int128 Sx = (__int128)sx;
-    const __int128 Sxx = (__int128)(((unsigned __int128)xx_hi << 64) | xx_lo);
-    const __int128 Sxi = (__int128)(((unsigned __int128)xi_hi << 64) | xi_lo);
+    const __int128 Sx = (__int128)v[0];
+    const __int128 Sxx = (__int128)(((unsigned __int128)v[2] << 32) + v[1]);
+    const __int128 Sxi = (__int128)(((unsigned __int128)v[4] << 32) + v[3]);
     const __int128 Si = N * (N - 1) / 2;
     const __int128 num = N * Sxi - Sx * Si;
     const __int128 den = N * Sxx - Sx * Sx;
@@ -102,20 +109,26 @@ __global__ void k_rmi_root(Pair2 P, uint64_t n, uint32_t nblocks) {
     M->n = n;
 }
 
-// bounds[l] = first rank whose key routes to a leaf >= l.
-__global__ void k_rmi_bounds(Pair2 P, uint64_t n) {
+// bounds[l] = first rank whose key routes to a leaf >= l, for l = 0..4096:
+// routing is monotone in the key (slope >= 0), so one bisection per leaf.
+__global__ void __launch_bounds__(256) k_rmi_bounds(Pair2 P, uint64_t n) {
     const int a = blockIdx.y;
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > BITS_RMI_LEAVES) return;
     const uint32_t* K = P.keys[a];
     const bits_rmi_model* M = P.model[a];
-    uint32_t* B = P.bounds[a];
     const float ra = M->root_a, rb = M->root_b;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        const int l = (int)rmi_route(ra, rb, K[i]);
-        const int lp = i ? (int)rmi_route(ra, rb, K[i - 1]) : -1;
-        for (int m = lp + 1; m <= l; ++m) B[m] = (uint32_t)i;
-        if (i == n - 1)
-            for (int m = l + 1; m <= (int)BITS_RMI_LEAVES; ++m) B[m] = (uint32_t)n;
+    uint64_t lo = 0, len = n;   // first i in [0, n) with route(K[i]) >= l, else n
+    while (len > 0) {
+        const uint64_t half = len >> 1;
+        if (rmi_route(ra, rb, K[lo + half]) < l) {
+            lo += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
     }
+    P.bounds[a][l] = (uint32_t)lo;
 }
 
 // ---------------------------------------------------------------- leaf training
@@ -434,11 +447,8 @@ int launch_rmi_build2(const uint32_t* keys0, const uint32_t* keys1, uint64_t n, 
     if (nb > (uint32_t)kSumBlocks) nb = kSumBlocks;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_rmi_sums, dim3(nb, 2), dim3(kThreads), 0, s, P, n);
-    hipLaunchKernelGGL(k_rmi_root, dim3(1), dim3(64), 0, s, P, n, nb);
-    uint32_t gb = (uint32_t)((n + 255) / 256);
-    if (gb > 8192u) gb = 8192u;
-    if (gb < 1) gb = 1;
-    hipLaunchKernelGGL(k_rmi_bounds, dim3(gb, 2), dim3(256), 0, s, P, n);
+    hipLaunchKernelGGL(k_rmi_root, dim3(1), dim3(2 * kWave), 0, s, P, n, nb);
+    hipLaunchKernelGGL(k_rmi_bounds, dim3((BITS_RMI_LEAVES + 256) / 256, 2), dim3(256), 0, s, P, n);
     TrainCfg tc{tr.epochs, tr.max_points, tr.lr, tr.beta1, tr.beta2};
     const size_t lds = (size_t)kTrainWaves * 2 * tc.max_points * sizeof(float);
     hipLaunchKernelGGL(k_rmi_train, dim3(BITS_RMI_LEAVES / kTrainWaves, 2), dim3(kTrainWaves * kWave), lds, s, P, tc);
