@@ -46,6 +46,7 @@ constexpr uint32_t kSliceWords = 12800;    // LDS slice capacity of the search k
 constexpr uint32_t kBuckets = 1024;
 static_assert(kSliceWords < 65536u, "bucket ranks are 16-bit");
 constexpr uint32_t kBinThreads = 1024;
+constexpr int ILP = 4;   // table entries each binning thread loads before it places them
 // A reference with few regions (a small B) would leave most of the chip idle
 // in the search; each region's records are then split over up to kMaxSplits
 // workgroups, aiming at kSearchWorkgroups per pass.
@@ -237,12 +238,20 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_place(
     const uint32_t ok = g.off[k], sh = g.shift, clen = g.off[k + 1] - g.off[k];
     const uint64_t gs = (sb + s) * na;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    for (uint32_t p = g0 + threadIdx.x; p < g1; p += blockDim.x) {
-        const uint2 q = packed[p];
-        if (!q.y) continue;
-        const uint32_t st = mc_place(gs + q.x, k0, k1, ok, clen - q.y + 1u);
-        const uint32_t lr = cr[(st - ok) >> sh];
-        if (lr < nr) atomicAdd(&h[lr], 1u);
+    for (uint32_t p0 = g0 + threadIdx.x; p0 < g1; p0 += ILP * blockDim.x) {
+        uint2 q[ILP];
+#pragma unroll
+        for (int u = 0; u < ILP; ++u) {
+            const uint32_t p = p0 + u * blockDim.x;
+            q[u] = p < g1 ? packed[p] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < ILP; ++u) {
+            if (!q[u].y) continue;
+            const uint32_t st = mc_place(gs + q[u].x, k0, k1, ok, clen - q[u].y + 1u);
+            const uint32_t lr = cr[(st - ok) >> sh];
+            if (lr < nr) atomicAdd(&h[lr], 1u);
+        }
     }
     __syncthreads();
     uint32_t* ss = seg_start + (uint64_t)s * nreg_max + rb;
@@ -253,14 +262,22 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_place(
     for (uint32_t j = threadIdx.x; j < nr; j += blockDim.x) ss[j] = g0 + h[j];
     __syncthreads();
     uint2* out = recs + (uint64_t)s * na;
-    for (uint32_t p = g0 + threadIdx.x; p < g1; p += blockDim.x) {
-        const uint2 q = packed[p];
-        if (!q.y) continue;
-        const uint32_t st = mc_place(gs + q.x, k0, k1, ok, clen - q.y + 1u);
-        const uint32_t lr = cr[(st - ok) >> sh];
-        if (lr >= nr) continue;
-        const uint32_t at = atomicAdd(&h[lr], 1u);
-        out[g0 + at] = make_uint2(st, st + (q.y - 1u));
+    for (uint32_t p0 = g0 + threadIdx.x; p0 < g1; p0 += ILP * blockDim.x) {
+        uint2 q[ILP];
+#pragma unroll
+        for (int u = 0; u < ILP; ++u) {
+            const uint32_t p = p0 + u * blockDim.x;
+            q[u] = p < g1 ? packed[p] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < ILP; ++u) {
+            if (!q[u].y) continue;
+            const uint32_t st = mc_place(gs + q[u].x, k0, k1, ok, clen - q[u].y + 1u);
+            const uint32_t lr = cr[(st - ok) >> sh];
+            if (lr >= nr) continue;
+            const uint32_t at = atomicAdd(&h[lr], 1u);
+            out[g0 + at] = make_uint2(st, st + (q[u].y - 1u));
+        }
     }
 }
 
