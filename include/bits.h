@@ -328,7 +328,8 @@ int bits_mc_binned_workspace(uint64_t na, uint64_t n, const uint32_t *chrom_len,
  * stream, same outputs bit for bit), ordered by region of the genome
  * rather than by query.  Each chromosome is cut into cells; a region is a
  * run of cells holding about 8192 keys of B_S and B_E together.  Per pass
- * of `batch` shuffles:
+ * of `batch` shuffles (fewer if batch * na would reach 2^32, so that a pass
+ * indexes its records in 32 bits):
  *   1. binning: the placements of every (shuffle, chromosome) are made,
  *      counted per region, made again and written as {start, end} records
  *      in region order (8 bytes per placement into d_ws);

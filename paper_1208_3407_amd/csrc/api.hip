@@ -629,8 +629,10 @@ int bits_mc_binned(const bits_ref* ref, const uint32_t* d_a_start, const uint32_
         BinTiming& tm = bin_timing();
         std::unique_lock<std::mutex> tl(tm.mu);
         tm.used = 0;
-        for (uint64_t sb = s0; W.L.ncells && sb < s1; sb += batch) {
-            const uint32_t nb = (uint32_t)((s1 - sb) < batch ? (s1 - sb) : batch);
+        // a pass indexes its records in 32 bits: at most (2^32 - 1) / na shuffles
+        const uint64_t pass = na ? std::min<uint64_t>(batch, 0xFFFFFFFFull / na) : batch;
+        for (uint64_t sb = s0; W.L.ncells && sb < s1; sb += pass) {
+            const uint32_t nb = (uint32_t)((s1 - sb) < pass ? (s1 - sb) : pass);
             hipEvent_t* ev = nullptr;
             if (tm.on) {
                 while (tm.ev.size() < tm.used + 4) {

@@ -43,7 +43,7 @@ constexpr uint32_t kSliceWords = 12800;    // LDS slice capacity of the search k
 // into at most kBuckets equal power-of-two buckets; word b of a table packs
 // the slice ranks of bucket b's first and last coordinate + 1 (16 bits each:
 // slices hold fewer than 2^16 keys).
-constexpr uint32_t kBuckets = 1024;
+constexpr uint32_t kBuckets = 1536;
 static_assert(kSliceWords < 65536u, "bucket ranks are 16-bit");
 constexpr uint32_t kBinThreads = 1024;
 constexpr int ILP = 4;   // table entries each binning thread loads before it places them
@@ -352,12 +352,13 @@ template <bool LDS, typename T>
 __device__ __forceinline__ void bin_count_region(const uint32_t* S, uint32_t ns, const uint32_t* E, uint32_t ne,
                                                  const uint32_t* __restrict__ bs, uint32_t n, uint32_t s_lo,
                                                  uint32_t e_lo, const Buckets& bk, const uint2* __restrict__ recs,
-                                                 uint64_t na, const uint64_t* pre, const uint32_t* sst, uint32_t nb,
+                                                 const uint32_t* pre, const uint32_t* base, uint32_t nb,
                                                  uint64_t q0, uint64_t q1, unsigned long long* acc) {
     const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const uint64_t steps = (q1 - q0 + kWave - 1) / kWave, per = (steps + nw - 1) / nw;
     const uint64_t p0 = q0 + (uint64_t)wv * per * kWave, p1 = min(q1, p0 + per * kWave);
     if (p0 >= p1) return;
+    // record p of the pass (p < pre[nb] < 2^32) is recs[base[s] + p], s its shuffle
     const uint32_t s_end = s_lo + ns;
     // shuffle of the wave's first record: the last s with pre[s] <= p0
     uint32_t sw = 0, hi = nb;
@@ -366,13 +367,13 @@ __device__ __forceinline__ void bin_count_region(const uint32_t* S, uint32_t ns,
         if (pre[mid] <= p0) sw = mid; else hi = mid;
     }
     for (uint64_t b = p0; b < p1; b += kWave) {
-        const uint64_t p = b + lane;
-        const bool valid = p < p1;
+        const bool valid = b + lane < p1;
+        const uint32_t p = (uint32_t)b + lane;
         uint32_t sl = sw;
         T v = 0;
         if (valid) {
             while (pre[sl + 1] <= p) ++sl;   // ends at sl < nb: p < pre[nb]
-            const uint2 r = recs[(uint64_t)sl * na + sst[sl] + (p - pre[sl])];
+            const uint2 r = recs[base[sl] + p];
             uint32_t first, last;
             if (LDS && r.y < bk.key_hi) {
                 // every key <= r.y is below key_hi, so inside the slice: the bucket's keys decide
@@ -409,36 +410,41 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_search(
     uint64_t na, uint32_t splits, unsigned long long* __restrict__ partial) {
     __shared__ uint32_t slice[kSliceWords];
     __shared__ uint32_t tabs[2 * kBuckets];
-    __shared__ uint64_t pre[BITS_MC_BIN_MAX_BATCH + 1];
-    __shared__ uint32_t sst[BITS_MC_BIN_MAX_BATCH];
+    __shared__ uint32_t pre[BITS_MC_BIN_MAX_BATCH + 1];
+    __shared__ uint32_t base[BITS_MC_BIN_MAX_BATCH];
     __shared__ unsigned long long acc[BITS_MC_BIN_MAX_BATCH];
-    __shared__ uint64_t w64[kBinThreads / kWave];
+    __shared__ uint32_t w32[kBinThreads / kWave];
     const uint32_t r = SPLIT ? blockIdx.x / splits : blockIdx.x, part = SPLIT ? blockIdx.x - r * splits : 0u;
     if (r >= *nreg_p) return;
     const RegionDesc d0 = desc[r], d1 = desc[r + 1];
     const uint32_t s_lo = d0.s_lo, e_lo = d0.e_lo;
     const uint32_t s_end = (uint32_t)min((uint64_t)d1.s_lo + kMargin, (uint64_t)n);
     const uint32_t ns = s_end - s_lo, ne = d1.e_lo - e_lo;
-    // per-shuffle segment starts and the prefix of their lengths (uint64: nb * na may pass 2^32)
-    uint32_t cnt = 0;
+    // per-shuffle prefix of the segment lengths, and each shuffle's record base: record p of
+    // the pass (in shuffle s) is recs[s * na + seg_start + (p - pre[s])]; nb * na < 2^32
+    uint32_t cnt = 0, sst = 0;
     if (threadIdx.x < nb) {
-        sst[threadIdx.x] = seg_start[(uint64_t)threadIdx.x * nreg_max + r];
+        sst = seg_start[(uint64_t)threadIdx.x * nreg_max + r];
         cnt = seg_cnt[(uint64_t)threadIdx.x * nreg_max + r];
         acc[threadIdx.x] = 0ull;
     }
     {
         const uint32_t lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-        uint64_t x = cnt;
+        uint32_t x = cnt;
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
-            const uint64_t y = __shfl_up(x, o);
+            const uint32_t y = __shfl_up(x, o);
             if (lane >= (uint32_t)o) x += y;
         }
-        if (lane == kWave - 1) w64[w] = x;
+        if (lane == kWave - 1) w32[w] = x;
         __syncthreads();
-        uint64_t before = 0;
-        for (uint32_t j = 0; j < w; ++j) before += w64[j];
-        if (threadIdx.x < nb) pre[threadIdx.x] = before + x - cnt;
+        uint32_t before = 0;
+        for (uint32_t j = 0; j < w; ++j) before += w32[j];
+        const uint32_t pr = before + x - cnt;
+        if (threadIdx.x < nb) {
+            pre[threadIdx.x] = pr;
+            base[threadIdx.x] = threadIdx.x * (uint32_t)na + sst - pr;
+        }
         if (threadIdx.x == nb - 1) pre[nb] = before + x;
     }
     const uint32_t eo = ns;   // E's first word
@@ -469,16 +475,16 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_search(
     // per-step sums fit 32 bits when 64 counts of at most n cannot reach 2^32
     const bool narrow = n < (1u << 26);
     if (in_lds && narrow)
-        bin_count_region<true, uint32_t>(slice, ns, slice + eo, ne, bs, n, s_lo, e_lo, bk, recs, na, pre, sst, nb,
+        bin_count_region<true, uint32_t>(slice, ns, slice + eo, ne, bs, n, s_lo, e_lo, bk, recs, pre, base, nb,
                                          q0, q1, acc);
     else if (in_lds)
-        bin_count_region<true, uint64_t>(slice, ns, slice + eo, ne, bs, n, s_lo, e_lo, bk, recs, na, pre, sst, nb,
+        bin_count_region<true, uint64_t>(slice, ns, slice + eo, ne, bs, n, s_lo, e_lo, bk, recs, pre, base, nb,
                                          q0, q1, acc);
     else if (narrow)
-        bin_count_region<false, uint32_t>(bs + s_lo, ns, be + e_lo, ne, bs, n, s_lo, e_lo, bk, recs, na, pre, sst,
+        bin_count_region<false, uint32_t>(bs + s_lo, ns, be + e_lo, ne, bs, n, s_lo, e_lo, bk, recs, pre, base,
                                           nb, q0, q1, acc);
     else
-        bin_count_region<false, uint64_t>(bs + s_lo, ns, be + e_lo, ne, bs, n, s_lo, e_lo, bk, recs, na, pre, sst,
+        bin_count_region<false, uint64_t>(bs + s_lo, ns, be + e_lo, ne, bs, n, s_lo, e_lo, bk, recs, pre, base,
                                           nb, q0, q1, acc);
     __syncthreads();
     if (threadIdx.x < nb)
