@@ -224,17 +224,14 @@ static int finish_ref(const bits_ref* r, const bits_train& tr, void* ws, hipStre
     } else {
         BITS_CHECK_HIP(launch_fill_u32(r->tree, (uint64_t)2 << r->depth, 0u, s));
     }
-    BITS_CHECK_HIP(launch_build_heads(r->bs, r->n, r->heads, s));
-    BITS_CHECK_HIP(launch_build_heads(r->be, r->n, r->heads + heads_len(r->n), s));
-    if (r->learned) {
+    uint32_t* he = r->heads + heads_len(r->n);
+    if (r->learned && r->n) {   // the learned build's pass over the keys also writes the heads
         bits_rmi_model* m = (bits_rmi_model*)r->rmi;
-        if (r->n == 0) {
-            BITS_CHECK_HIP(launch_fill_u32((uint32_t*)m, 2 * sizeof(bits_rmi_model) / 4, 0u, s));
-        } else {
-            const int rc = launch_rmi_build2(r->bs, r->be, r->n, m, m + 1, tr, ws, s);
-            if (rc != BITS_OK) return rc;
-        }
+        return launch_rmi_build2(r->bs, r->be, r->n, m, m + 1, r->heads, he, tr, ws, s);
     }
+    BITS_CHECK_HIP(launch_build_heads(r->bs, r->n, r->heads, s));
+    BITS_CHECK_HIP(launch_build_heads(r->be, r->n, he, s));
+    if (r->learned) BITS_CHECK_HIP(launch_fill_u32((uint32_t*)r->rmi, 2 * sizeof(bits_rmi_model) / 4, 0u, s));
     return BITS_OK;
 }
 

@@ -314,8 +314,10 @@ hipError_t launch_enumerate(const uint32_t* starts, const uint32_t* ends, const 
 
 // rmi.hip
 size_t rmi_workspace_bytes();
+// Also writes the line heads of both arrays (heads_len(n) words each).
 int launch_rmi_build2(const uint32_t* keys0, const uint32_t* keys1, uint64_t n, bits_rmi_model* m0,
-                      bits_rmi_model* m1, const bits_train& tr, void* ws, hipStream_t s);
+                      bits_rmi_model* m1, uint32_t* heads0, uint32_t* heads1, const bits_train& tr, void* ws,
+                      hipStream_t s);
 hipError_t launch_rmi_leaf_grad(const float* u, const float* t, uint32_t m, const float* params, float* grad,
                                 float* loss, hipStream_t s);
 

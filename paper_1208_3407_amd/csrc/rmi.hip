@@ -34,6 +34,7 @@ struct Pair2 {
     bits_rmi_model* model[2];
     uint32_t* bounds[2];   // [4097] first rank of every leaf, bounds[4096] = n
     Sums* sums[2];
+    uint32_t* heads[2];    // line heads of the array, heads_len(n) words
 };
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
@@ -42,21 +43,41 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-// Exact sums over the keys: sum x, sum x^2, sum x*i (i = rank), as split
-// halves (Sums); one read of the sorted keys.
-__global__ void __launch_bounds__(kThreads) k_rmi_sums(Pair2 P, uint64_t n) {
+__device__ __forceinline__ void add_key(unsigned long long (&v)[5], uint32_t x, uint32_t i) {
+    const uint64_t xx = (uint64_t)x * x, xi = (uint64_t)x * i;   // i < n < 2^32
+    v[0] += x;
+    v[1] += (uint32_t)xx;
+    v[2] += (uint32_t)(xx >> 32);
+    v[3] += (uint32_t)xi;
+    v[4] += (uint32_t)(xi >> 32);
+}
+
+// One read of the sorted keys: exact sums x, x^2, x*i (i = rank) as split
+// halves (Sums), and the line heads (heads[j] = keys[32 j], then 0xFFFFFFFF
+// up to hl), four keys per 16-byte load.
+__global__ void __launch_bounds__(kThreads) k_rmi_sums(Pair2 P, uint64_t n, uint64_t hl) {
     const int a = blockIdx.y;
     const uint32_t* K = P.keys[a];
+    uint32_t* H = P.heads[a];
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (uint64_t)gridDim.x * blockDim.x;
     unsigned long long v[5] = {0ull, 0ull, 0ull, 0ull, 0ull};
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t x = K[i];
-        const uint64_t xx = (uint64_t)x * x, xi = (uint64_t)x * (uint32_t)i;   // i < n < 2^32
-        v[0] += x;
-        v[1] += (uint32_t)xx;
-        v[2] += (uint32_t)(xx >> 32);
-        v[3] += (uint32_t)xi;
-        v[4] += (uint32_t)(xi >> 32);
+    const uint64_t nq = n / 4;
+    const uint4* K4 = reinterpret_cast<const uint4*>(K);   // the sorted arrays are 256-byte aligned
+    for (uint64_t c = gid; c < nq; c += stride) {
+        const uint4 x = K4[c];
+        const uint32_t i0 = (uint32_t)(4 * c);
+        add_key(v, x.x, i0);
+        add_key(v, x.y, i0 + 1u);
+        add_key(v, x.z, i0 + 2u);
+        add_key(v, x.w, i0 + 3u);
+        if ((c & 7u) == 0) H[c >> 3] = x.x;
     }
+    for (uint64_t i = 4 * nq + gid; i < n; i += stride) {
+        const uint32_t x = K[i];
+        add_key(v, x, (uint32_t)i);
+        if ((i & 31u) == 0) H[i >> 5] = x;
+    }
+    for (uint64_t j = (n + 31) / 32 + gid; j < hl; j += stride) H[j] = 0xFFFFFFFFu;
     __shared__ unsigned long long r[kWaves][5];
     const uint32_t lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
@@ -432,8 +453,11 @@ size_t rmi_workspace_bytes() {
 
 // Builds the learned index of BOTH sorted arrays in the same launches.
 int launch_rmi_build2(const uint32_t* keys0, const uint32_t* keys1, uint64_t n, bits_rmi_model* m0,
-                      bits_rmi_model* m1, const bits_train& tr, void* ws, hipStream_t s) {
+                      bits_rmi_model* m1, uint32_t* heads0, uint32_t* heads1, const bits_train& tr, void* ws,
+                      hipStream_t s) {
     Pair2 P;
+    P.heads[0] = heads0;
+    P.heads[1] = heads1;
     char* b = (char*)ws;
     P.keys[0] = keys0;
     P.keys[1] = keys1;
@@ -446,7 +470,7 @@ int launch_rmi_build2(const uint32_t* keys0, const uint32_t* keys1, uint64_t n, 
     uint32_t nb = (uint32_t)((n + kThreads - 1) / kThreads);
     if (nb > (uint32_t)kSumBlocks) nb = kSumBlocks;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_rmi_sums, dim3(nb, 2), dim3(kThreads), 0, s, P, n);
+    hipLaunchKernelGGL(k_rmi_sums, dim3(nb, 2), dim3(kThreads), 0, s, P, n, heads_len(n));
     hipLaunchKernelGGL(k_rmi_root, dim3(1), dim3(2 * kWave), 0, s, P, n, nb);
     hipLaunchKernelGGL(k_rmi_bounds, dim3((BITS_RMI_LEAVES + 256) / 256, 2), dim3(256), 0, s, P, n);
     TrainCfg tc{tr.epochs, tr.max_points, tr.lr, tr.beta1, tr.beta2};
