@@ -293,6 +293,7 @@ struct TrainCfg {
 };
 
 constexpr int kTrainWaves = 2;
+constexpr int kErrBatch = 8;   // keys per lane loaded together in the error-window pass
 
 // Dynamic LDS: 2 * tc.max_points floats per wave.
 __global__ void __launch_bounds__(kTrainWaves * kWave) k_rmi_train(Pair2 P, TrainCfg tc) {
@@ -389,14 +390,26 @@ __global__ void __launch_bounds__(kTrainWaves * kWave) k_rmi_train(Pair2 P, Trai
     // Error window over every key of the leaf (first occurrence of each
     // value; x == kmin is answered without a search), with the query-time
     // prediction arithmetic on the stored model.
+    // kErrBatch keys (and their predecessors) are loaded per lane before any is
+    // evaluated, so the loads of a batch are in flight together.
     int32_t over = 0, under = 0;
-    for (uint32_t i = rlo + lane; i < rlo + cnt; i += kWave) {
-        const uint32_t x = K[i];
-        if (x == kmin) continue;
-        if (K[i - 1] == x) continue;   // i > rlo here because x > kmin
-        const int32_t e = rmi_pred_offset(q, cnt, kinv, x - kmin) - (int32_t)(i - rlo);
-        over = max(over, e);
-        under = max(under, -e);
+    const uint32_t rend = rlo + cnt;
+    for (uint32_t i0 = rlo + lane; i0 < rend; i0 += kErrBatch * kWave) {
+        uint32_t xs[kErrBatch], xp[kErrBatch];
+#pragma unroll
+        for (int k = 0; k < kErrBatch; ++k) {
+            const uint32_t i = i0 + (uint32_t)k * kWave;
+            xs[k] = i < rend ? K[i] : kmin;
+            xp[k] = (i < rend && i > rlo) ? K[i - 1] : kmin;
+        }
+#pragma unroll
+        for (int k = 0; k < kErrBatch; ++k) {
+            const uint32_t i = i0 + (uint32_t)k * kWave, x = xs[k];
+            if (x == kmin || xp[k] == x) continue;   // past the leaf, the leaf's first key, or a repeat
+            const int32_t e = rmi_pred_offset(q, cnt, kinv, x - kmin) - (int32_t)(i - rlo);
+            over = max(over, e);
+            under = max(under, -e);
+        }
     }
     over = min(wave_max_i32(over), 65535);
     under = min(wave_max_i32(under), 65535);
