@@ -39,7 +39,7 @@ constexpr uint64_t kLbPrefix = 1ull << 40;
 // Polls of a predecessor's word before giving up (the walk cannot deadlock:
 // tiles are taken in order, so every tile waited on is held by a running
 // workgroup; the bound only turns a fault into BITS_FLAG_SORT, not a hang).
-constexpr uint32_t kLbSpinLimit = 1u << 22;
+constexpr uint32_t kLbSpinLimit = 1u << 20;
 constexpr int kLbBatch = 8;   // predecessor words loaded at once
 
 struct SegDesc {
