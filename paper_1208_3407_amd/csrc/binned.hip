@@ -12,7 +12,10 @@
 //   binning  per (shuffle, chromosome): the placements of the chromosome's
 //            queries are made (the Philox stream of the other Monte-Carlo
 //            kernels), counted per region, made again and written, with their
-//            ends, in region order: one segment per (shuffle, region);
+//            ends, in region order: one segment per (shuffle, region).  When
+//            the chromosome has many regions, the second sweep goes in chunks
+//            that are counting-sorted by region in LDS and written out in
+//            region runs, so that a record line is filled in one go;
 //   search   per region (or per share of a region's records when regions
 //            are few): both slices are staged in LDS (B_S with kMargin keys
 //            past the region's end, for ends that cross it), with a table of
@@ -209,28 +212,49 @@ __global__ void __launch_bounds__(256) k_bin_pack(const uint32_t* __restrict__ s
         packed[p] = make_uint2(idx[p], span[p] ? len[p] : 0u);
 }
 
+// Staged binning (second sweep): chromosomes with kStageMinRegions..kStageRegions
+// regions; kStageRecs records per chunk, so that the workgroup's LDS (about 76 KB)
+// still lets two workgroups share a CU.
+constexpr uint32_t kStageRegions = 2048;
+constexpr uint32_t kStageMinRegions = 128;
+constexpr uint32_t kStageRecs = 5632;      // 44 KB
+constexpr int kStagePer = (kStageRecs + kBinThreads - 1) / kBinThreads;
+
+// Entry j of an array of 16-bit values packed two per word.
+__device__ __forceinline__ uint32_t half16(const uint32_t* w, uint32_t j) {
+    return (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+}
+
 // Binning of shuffles [sb, sb + nb): workgroup (k, s) makes the placements of
 // chromosome k's queries (table positions [cursor[k] - hist[k], cursor[k]))
 // in shuffle sb + s, counts them per region, writes the segment table of
 // (s, every region of k), and writes the records {start, end} in region
-// order to recs[s * na + table position range].
-__global__ void __launch_bounds__(kBinThreads) k_bin_place(
+// order to recs[s * na + table position range], either one by one (few
+// regions, or more than kStageRegions) or chunk by chunk through LDS.
+// (8 waves per SIMD: two workgroups per CU, at most 64 VGPRs.)
+__global__ void __launch_bounds__(kBinThreads, 8) k_bin_place(
     BinGeom g, const uint2* __restrict__ packed, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ cursor,
     uint64_t na, uint64_t seed, uint64_t sb, uint32_t nb, const uint32_t* __restrict__ cell_region,
     const uint64_t* __restrict__ offsets, uint32_t nreg_max, uint32_t* __restrict__ seg_start,
     uint32_t* __restrict__ seg_cnt, uint2* __restrict__ recs) {
     __shared__ uint16_t cr[kMaxCells];
-    __shared__ uint32_t h[kMaxCells];
+    __shared__ uint32_t hs[kStageRegions];          // segment cursors (staged path)
+    __shared__ uint32_t cc[kStageRegions / 2];      // chunk counts, 16 bits each
+    __shared__ uint32_t co[kStageRegions / 2];      // chunk offsets (exclusive), 16 bits each
+    __shared__ uint2 stage[kStageRecs];             // the chunk's records in region order; h of the direct path
     __shared__ uint32_t wsum[kBinThreads / kWave];
+    __shared__ uint32_t staged_total;
     const uint32_t k = blockIdx.x / nb, s = blockIdx.x - k * nb;
     const uint32_t c0 = g.cb[k], nc = g.cb[k + 1] - c0;
-    if (nc == 0) return;   // no cells: no regions, no queries (an empty chromosome holds none)
+    if (nc == 0) return;
     const uint32_t nreg = (uint32_t)offsets[g.cb[g.n_chrom]];
     const uint32_t rb = cell_region[c0];
     const uint32_t rl = (k + 1 < g.n_chrom && g.cb[k + 1] < g.cb[g.n_chrom]) ? cell_region[g.cb[k + 1]] : nreg;
-    // regions of chromosome k (<= nc <= kMaxCells; the clamps only matter for an inconsistent
-    // table, which k_bin_regions has already flagged)
     const uint32_t nr = rl > rb ? min(min(rl - rb, nc), nreg_max - rb) : 0u;
+    // staging pays when a chromosome spreads its records over many regions (many open
+    // record lines); with few regions the direct writes already merge in L2
+    const bool staged = nr >= kStageMinRegions && nr <= kStageRegions;
+    uint32_t* h = staged ? hs : reinterpret_cast<uint32_t*>(stage);   // kMaxCells words fit the stage buffer
     for (uint32_t j = threadIdx.x; j < nc; j += blockDim.x) cr[j] = (uint16_t)(cell_region[c0 + j] - rb);
     for (uint32_t j = threadIdx.x; j < nr; j += blockDim.x) h[j] = 0u;
     __syncthreads();
@@ -262,22 +286,97 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_place(
     for (uint32_t j = threadIdx.x; j < nr; j += blockDim.x) ss[j] = g0 + h[j];
     __syncthreads();
     uint2* out = recs + (uint64_t)s * na;
-    for (uint32_t p0 = g0 + threadIdx.x; p0 < g1; p0 += ILP * blockDim.x) {
-        uint2 q[ILP];
+    if (!staged) {
+        for (uint32_t p0 = g0 + threadIdx.x; p0 < g1; p0 += ILP * blockDim.x) {
+            uint2 q[ILP];
 #pragma unroll
-        for (int u = 0; u < ILP; ++u) {
-            const uint32_t p = p0 + u * blockDim.x;
-            q[u] = p < g1 ? packed[p] : make_uint2(0u, 0u);
+            for (int u = 0; u < ILP; ++u) {
+                const uint32_t p = p0 + u * blockDim.x;
+                q[u] = p < g1 ? packed[p] : make_uint2(0u, 0u);
+            }
+#pragma unroll
+            for (int u = 0; u < ILP; ++u) {
+                if (!q[u].y) continue;
+                const uint32_t st = mc_place(gs + q[u].x, k0, k1, ok, clen - q[u].y + 1u);
+                const uint32_t lr = cr[(st - ok) >> sh];
+                if (lr >= nr) continue;
+                const uint32_t at = atomicAdd(&h[lr], 1u);
+                out[g0 + at] = make_uint2(st, st + (q[u].y - 1u));
+            }
         }
+        return;
+    }
+    // staged: chunks of kStageRecs table entries are placed, counting-sorted by region in
+    // LDS, and written out in region runs
+    const uint32_t nw2 = (nr + 1) >> 1;
+    for (uint32_t j = threadIdx.x; j < nw2; j += blockDim.x) cc[j] = 0u;
+    __syncthreads();
+    for (uint32_t cb = g0; cb < g1; cb += kStageRecs) {
+        const uint32_t ce = min(g1, cb + kStageRecs);
+        uint32_t st_[kStagePer], len_[kStagePer], key_[kStagePer];   // key = lr << 16 | rank, or ~0
 #pragma unroll
-        for (int u = 0; u < ILP; ++u) {
-            if (!q[u].y) continue;
-            const uint32_t st = mc_place(gs + q[u].x, k0, k1, ok, clen - q[u].y + 1u);
+        for (int u = 0; u < kStagePer; ++u) {
+            const uint32_t p = cb + threadIdx.x + (uint32_t)u * blockDim.x;
+            const uint2 q = p < ce ? packed[p] : make_uint2(0u, 0u);
+            key_[u] = 0xFFFFFFFFu;
+            st_[u] = 0u;
+            len_[u] = q.y;
+            if (!q.y) continue;
+            const uint32_t st = mc_place(gs + q.x, k0, k1, ok, clen - q.y + 1u);
             const uint32_t lr = cr[(st - ok) >> sh];
             if (lr >= nr) continue;
-            const uint32_t at = atomicAdd(&h[lr], 1u);
-            out[g0 + at] = make_uint2(st, st + (q[u].y - 1u));
+            const uint32_t sft = 16u * (lr & 1u);
+            const uint32_t old = atomicAdd(&cc[lr >> 1], 1u << sft);
+            st_[u] = st;
+            key_[u] = (lr << 16) | ((old >> sft) & 0xFFFFu);
         }
+        __syncthreads();
+        // exclusive offsets of the chunk's region counts (two per word), in place
+        {
+            const uint32_t wv = threadIdx.x < nw2 ? cc[threadIdx.x] : 0u;
+            const uint32_t a0 = wv & 0xFFFFu, a1 = wv >> 16, tsum = a0 + a1;
+            const uint32_t lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+            uint32_t x = tsum;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o);
+                if (lane >= (uint32_t)o) x += y;
+            }
+            if (lane == kWave - 1) wsum[w] = x;
+            __syncthreads();
+            uint32_t pre = 0, tot = 0;
+            for (uint32_t j = 0; j < kBinThreads / kWave; ++j) {
+                if (j < w) pre += wsum[j];
+                tot += wsum[j];
+            }
+            pre += x - tsum;
+            if (threadIdx.x < nw2) co[threadIdx.x] = pre | ((pre + a0) << 16);
+            if (threadIdx.x == 0) staged_total = tot;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kStagePer; ++u) {
+            if (key_[u] == 0xFFFFFFFFu) continue;
+            const uint32_t lr = key_[u] >> 16;
+            stage[half16(co, lr) + (key_[u] & 0xFFFFu)] = make_uint2(st_[u], st_[u] + (len_[u] - 1u));
+        }
+        __syncthreads();
+        const uint32_t tot = staged_total;
+        for (uint32_t j = threadIdx.x; j < tot; j += blockDim.x) {
+            const uint2 rec = stage[j];
+            const uint32_t lr = cr[(rec.x - ok) >> sh];
+            out[g0 + hs[lr] + (j - half16(co, lr))] = rec;
+        }
+        __syncthreads();
+        // advance the cursors by the chunk's counts and clear the counters (each thread its
+        // own counter words)
+        for (uint32_t j = threadIdx.x; j < nw2; j += blockDim.x) {
+            const uint32_t c = cc[j];
+            hs[2 * j] += c & 0xFFFFu;
+            if (2 * j + 1 < nr) hs[2 * j + 1] += c >> 16;
+            cc[j] = 0u;
+        }
+        __syncthreads();
     }
 }
 

@@ -78,6 +78,41 @@ def test_binned_many_regions_and_long_queries():
     check(L, a_s, a_e, b_s, b_e, 3, 0, 9, 4)
 
 
+def test_binned_staged_chunks_and_direct_chromosomes():
+    """A chromosome with about 500 regions (its second binning sweep goes through LDS
+    in several chunks) beside one with few regions (records written one by one), in
+    the same call; queries up to 50 kbp."""
+    note("case: binned staged chunks + direct")
+    r = np.random.default_rng(21)
+    L = np.array([50_000_000, 2_000_000], np.uint32)
+    nb = 2_000_000
+    centres = r.integers(0, 49_000_000, 300)
+    b_s = np.concatenate([r.integers(0, 49_990_000, nb // 2),
+                          np.clip(centres[r.integers(0, 300, nb // 2)] + r.normal(0, 40_000, nb // 2), 0,
+                                  49_990_000).astype(np.int64),
+                          50_000_000 + r.integers(0, 1_990_000, 5000)]).astype(np.uint32)
+    b_e = b_s + r.integers(0, 3000, len(b_s)).astype(np.uint32)
+    na = 20_000
+    a_s = np.concatenate([r.integers(0, 49_940_000, na), 50_000_000 + r.integers(0, 1_940_000, 2000)]).astype(np.uint32)
+    a_e = a_s + r.integers(0, 50_000, len(a_s)).astype(np.uint32)
+    check(L, a_s, a_e, b_s, b_e, 5, 3, 9, 4)
+
+
+def test_binned_more_regions_than_staging_holds():
+    """A chromosome with more regions than the staged binning's tables hold (about
+    2200): its records are written one by one through the same kernel."""
+    note("case: binned > 2048 regions on one chromosome")
+    r = np.random.default_rng(22)
+    L = np.array([200_000_000], np.uint32)
+    nb = 9_000_000
+    b_s = r.integers(0, 199_990_000, nb).astype(np.uint32)
+    b_e = b_s + r.integers(0, 2000, nb).astype(np.uint32)
+    na = 3000
+    a_s = r.integers(0, 199_900_000, na).astype(np.uint32)
+    a_e = a_s + r.integers(0, 20_000, na).astype(np.uint32)
+    check(L, a_s, a_e, b_s, b_e, 8, 0, 4, 4, against_pvalue=False)
+
+
 def test_binned_oversize_region_and_empty_chromosomes():
     """Empty chromosomes between non-empty ones, 12,000 intervals of B on one
     coordinate (a region too large for LDS, searched in HBM), B keys past the
