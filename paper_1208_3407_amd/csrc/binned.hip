@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_bin_place(
             key_[u] = (lr << 16) | ((old >> sft) & 0xFFFFu);
         }
         __syncthreads();
-        // exclusive offsets of the chunk's region counts (two per word), in place
+        // exclusive offsets of the chunk's region counts (two per word) into co
         {
             const uint32_t wv = threadIdx.x < nw2 ? cc[threadIdx.x] : 0u;
             const uint32_t a0 = wv & 0xFFFFu, a1 = wv >> 16, tsum = a0 + a1;
