@@ -601,8 +601,11 @@ def main():
     pass_ms = (stage_ms["place"] + stage_ms["search"] + stage_ms["reduce"]) / passes
     _, lds_instr = load_counters("k_bin_search", placements)
     lds_ach = None if lds_instr is None else lds_instr * 256.0 / (launch_ms["k_bin_search"] / 1e3) / 1e9
-    valu_instr = load_valu("k_bin_search", placements)
-    valu_ach = None if valu_instr is None else valu_instr / (launch_ms["k_bin_search"] / 1e3) / 1e9
+    valu_ach = {}
+    for kname in ("k_bin_place", "k_bin_search"):
+        instr = load_valu(kname, placements)
+        valu_ach[kname] = None if instr is None else instr / (launch_ms[kname] / 1e3) / 1e9
+    other = "k_bin_search" if dom == "k_bin_place" else "k_bin_place"
     learned_achieved = BYTES_PER_EVAL_LEARNED * N_SHUF * N_MC / (t_mc_learned / 1e3) / 1e9
 
     configs = None if args.no_configs else other_configs(bits, dev, timed, train)
@@ -654,18 +657,22 @@ def main():
                      "peak_measured_copy": copy_gbs, "frac_of_measured": achieved / copy_gbs,
                      "compulsory_bytes_per_pass": compulsory,
                      "frac_compulsory_per_pass": compulsory / (pass_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-                     "limiter": ("LDS (probe bank conflicts) and VALU issue" if dom == "k_bin_search" else
-                                 "partly written lines of the scattered records")},
+                     "limiter": ("VALU issue: the two bucket searches and the per-shuffle sums"
+                                 if dom == "k_bin_search" else
+                                 "VALU issue: two Philox draws per placement and the LDS ranking of each chunk; "
+                                 "the record writes are about 1.6x the design bytes (partly written lines)")},
         "roofline_lds": {"bound": "lds", "kernel": "k_bin_search", "achieved": lds_ach, "peak": LDS_PEAK_GBS,
                          "unit": "GB/s", "frac": None if lds_ach is None else lds_ach / LDS_PEAK_GBS,
                          "launch_ms": launch_ms["k_bin_search"],
                          "bytes": "LDS instructions per launch (counters) x 256 B (64 lanes x 4 B)"},
-        "roofline_valu": {"bound": "alu", "kernel": "k_bin_search", "achieved": valu_ach, "peak": VALU_PEAK_G,
+        "roofline_valu": {"bound": "alu", "kernel": dom, "achieved": valu_ach[dom], "peak": VALU_PEAK_G,
                           "unit": "G wave-instructions/s",
-                          "frac": None if valu_ach is None else valu_ach / VALU_PEAK_G,
-                          "launch_ms": launch_ms["k_bin_search"],
+                          "frac": None if valu_ach[dom] is None else valu_ach[dom] / VALU_PEAK_G,
+                          "launch_ms": launch_ms[dom],
                           "bytes": "VALU wave-instructions per launch (counters); peak: one wave64 VALU "
-                                   "instruction per CU per clock, 256 CUs, 2.4 GHz"},
+                                   "instruction per CU per clock, 256 CUs, 2.4 GHz",
+                          "other": {"kernel": other, "achieved": valu_ach[other], "launch_ms": launch_ms[other],
+                                    "frac": None if valu_ach[other] is None else valu_ach[other] / VALU_PEAK_G}},
         "roofline_learned_mc": {"bound": "hbm", "kernel": "k_mc_sorted (query-ordered learned-index Monte-Carlo, "
                                 "outside the timed region)", "achieved": learned_achieved, "peak": HBM_PEAK_GBS,
                                 "unit": "GB/s", "frac": learned_achieved / HBM_PEAK_GBS,
