@@ -28,9 +28,18 @@ constexpr int kThreads = 256;                  // histogram, scan and copy kerne
 constexpr int kWaves = kThreads / kWave;
 constexpr int kSweepThreads = 1024;            // one pass of the sort
 constexpr int kSweepWaves = kSweepThreads / kWave;
-constexpr uint32_t kPerWave = 1024;            // keys per wave per tile
-constexpr uint32_t kTile = kPerWave * kSweepWaves;  // 16384 keys per tile
-constexpr int kRounds = kPerWave / kWave;      // 16 rounds of 64 keys
+// Keys per wave per tile: 20 rounds of 64 keys held in registers (20480-key
+// tiles) for a keys-only sort; 16 rounds (16384-key tiles) when values ride
+// along, so that keys and values both fit the tile's LDS.
+template <bool VALS>
+struct TileShape {
+    static constexpr uint32_t kPerWave = VALS ? 1024u : 1280u;
+    static constexpr uint32_t kTile = kPerWave * kSweepWaves;
+    static constexpr int kRounds = (int)(kPerWave / kWave);
+};
+__host__ __device__ constexpr uint32_t tile_keys(bool vals) {
+    return vals ? TileShape<true>::kTile : TileShape<false>::kTile;
+}
 // Look-back words, one per (tile, digit): bits 0-31 the count, bits 32-39
 // the pass (1 + p; 0 = not yet published in this call), bit 40 set once the
 // count is the inclusive prefix over the segment's tiles up to this one
@@ -124,7 +133,8 @@ __global__ void k_write_descs(SegDesc* dst, DescChunk chunk, uint32_t count) {
 // Workgroup b walks a contiguous range of tiles, accumulating in LDS and
 // flushing when the segment changes.
 __global__ void __launch_bounds__(kThreads) k_hist_all(const SegDesc* __restrict__ descs, uint32_t nseg,
-                                                       uint32_t ntiles, uint32_t* __restrict__ seg_hist) {
+                                                       uint32_t ntiles, uint32_t tile,
+                                                       uint32_t* __restrict__ seg_hist) {
     __shared__ uint32_t h[4][256];
     const uint32_t t0 = (uint32_t)((uint64_t)ntiles * blockIdx.x / gridDim.x);
     const uint32_t t1 = (uint32_t)((uint64_t)ntiles * (blockIdx.x + 1) / gridDim.x);
@@ -146,8 +156,8 @@ __global__ void __launch_bounds__(kThreads) k_hist_all(const SegDesc* __restrict
             cur = s;
         }
         const SegDesc d = descs[s];
-        const uint32_t begin = (t - d.tile0) * kTile;
-        const uint32_t cnt = min(kTile, d.n - begin);
+        const uint32_t begin = (t - d.tile0) * tile;
+        const uint32_t cnt = min(tile, d.n - begin);
         const uint32_t* src = d.in + begin;
         for (uint32_t k = threadIdx.x; k < cnt; k += kThreads) {
             const uint32_t key = src[k];
@@ -230,7 +240,7 @@ __device__ __forceinline__ uint32_t block_excl_scan_n(uint32_t v, uint32_t* tmp)
 }
 
 // One pass of the sort over one tile (taken from the pass's counter).  Wave
-// w ranks keys [w*1024, (w+1)*1024) of the tile in 16 rounds; within a
+// w ranks keys [w*kPerWave, (w+1)*kPerWave) of the tile in kRounds rounds; within a
 // round, lanes holding the same digit are found with 8 ballots (each folded
 // into the lane's peer mask by one v_bitop3 per half) and ranked by lane
 // order.  The tile's digit counts are published, the exclusive prefix
@@ -242,6 +252,8 @@ __global__ void __launch_bounds__(kSweepThreads) k_onesweep(const SegDesc* __res
                                                             unsigned long long* __restrict__ lb, uint32_t ntiles,
                                                             const uint32_t* __restrict__ seg_pre) {
     if (!plan->active[p]) return;
+    constexpr uint32_t kPerWave = TileShape<VALS>::kPerWave, kTile = TileShape<VALS>::kTile;
+    constexpr int kRounds = TileShape<VALS>::kRounds;
     __shared__ uint32_t keys_lds[kTile];
     __shared__ uint32_t vals_lds[VALS ? kTile : 1];
     __shared__ uint32_t wcnt[kSweepWaves][256];
@@ -313,7 +325,12 @@ __global__ void __launch_bounds__(kSweepThreads) k_onesweep(const SegDesc* __res
                            __HIP_MEMORY_SCOPE_AGENT);
     }
     const uint32_t ds = block_excl_scan_n<kSweepWaves>(dg < 256 ? tot : 0u, tmp);
-    if (dg < 256) dstart[dg] = ds;
+    if (dg < 256) {
+        // wave offsets become tile offsets: each key then needs one LDS read
+        dstart[dg] = ds;
+#pragma unroll
+        for (int k = 0; k < kSweepWaves; ++k) wcnt[k][dg] += ds;
+    }
     __syncthreads();
     // the tile sorted by digit in LDS (needs only tile-local offsets)
 #pragma unroll
@@ -321,7 +338,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_onesweep(const SegDesc* __res
         const uint32_t idx = (uint32_t)w * kPerWave + (uint32_t)r * kWave + lane;
         if (idx < cnt) {
             const uint32_t kd = (key[r] >> shift) & 255u;
-            const uint32_t at = dstart[kd] + wcnt[w][kd] + rank[r];
+            const uint32_t at = wcnt[w][kd] + rank[r];
             keys_lds[at] = key[r];
             if constexpr (VALS) {
                 if (vals) vals_lds[at] = iota ? begin + idx : vsrc[idx];
@@ -381,13 +398,14 @@ __global__ void __launch_bounds__(kSweepThreads) k_onesweep(const SegDesc* __res
 }
 
 // When no digit varies the input is already sorted (all keys equal): copy.
-__global__ void k_copy_if_idle(const SegDesc* __restrict__ descs, uint32_t nseg, const SortPlan* __restrict__ plan) {
+__global__ void k_copy_if_idle(const SegDesc* __restrict__ descs, uint32_t nseg, const SortPlan* __restrict__ plan,
+                               uint32_t tile) {
     if (plan->n_active) return;
     const uint32_t t = blockIdx.x;
     const uint32_t s = seg_of_tile(descs, nseg, t);
     const SegDesc d = descs[s];
-    const uint32_t begin = (t - d.tile0) * kTile;
-    const uint32_t cnt = min(kTile, d.n - begin);
+    const uint32_t begin = (t - d.tile0) * tile;
+    const uint32_t cnt = min(tile, d.n - begin);
     for (uint32_t k = threadIdx.x; k < cnt; k += kThreads) {
         d.out[begin + k] = d.in[begin + k];
         if (d.vmode) d.vout[begin + k] = d.vmode == 2 ? begin + k : d.vin[begin + k];
@@ -426,9 +444,12 @@ struct WsLayout {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static WsLayout ws_layout(const uint64_t* n, uint32_t nseg, const uint32_t* vmode) {
+    bool any_vals = false;
+    for (uint32_t s = 0; s < nseg; ++s) any_vals |= vmode && vmode[s];
+    const uint64_t tile = tile_keys(any_vals);
     uint64_t ntiles = 0, nkeys = 0, nvals = 0;
     for (uint32_t s = 0; s < nseg; ++s) {
-        ntiles += (n[s] + kTile - 1) / kTile;
+        ntiles += (n[s] + tile - 1) / tile;
         nkeys += n[s];
         if (vmode && vmode[s]) nvals += n[s];
     }
@@ -463,6 +484,7 @@ int launch_sort(const SortSeg* segs, uint32_t nseg, void* ws, size_t ws_bytes, h
     const WsLayout L = ws_layout(ns.data(), nseg, vm.data());
     bool any_vals = false;
     for (uint32_t i = 0; i < nseg; ++i) any_vals |= vm[i] != 0;
+    const uint32_t tile = tile_keys(any_vals);
     if (ws_bytes < L.total) return BITS_E_WORKSPACE;
     char* base = (char*)ws;
     SegDesc* descs = (SegDesc*)(base + L.descs);
@@ -495,7 +517,7 @@ int launch_sort(const SortSeg* segs, uint32_t nseg, void* ws, size_t ws_bytes, h
                 ch.d[i].vout = g.vout;
                 voff += g.n;
             }
-            tile0 += (uint32_t)((g.n + kTile - 1) / kTile);
+            tile0 += (uint32_t)((g.n + tile - 1) / tile);
             koff += g.n;
         }
         hipLaunchKernelGGL(k_write_descs, dim3(1), dim3(128), 0, s, descs + c0, ch, cnt);
@@ -510,7 +532,7 @@ int launch_sort(const SortSeg* segs, uint32_t nseg, void* ws, size_t ws_bytes, h
 
     BITS_CHECK_HIP(launch_fill_u64(lb, (uint64_t)ntiles * 256, 0ull, s));
     const uint32_t hg = ntiles < 2048u ? ntiles : 2048u;
-    hipLaunchKernelGGL(k_hist_all, dim3(hg), dim3(kThreads), 0, s, descs, nseg, ntiles, seg_hist);
+    hipLaunchKernelGGL(k_hist_all, dim3(hg), dim3(kThreads), 0, s, descs, nseg, ntiles, tile, seg_hist);
     hipLaunchKernelGGL(k_seg_scan, dim3(nseg * 4), dim3(kThreads), 0, s, seg_hist, seg_pre, plan);
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, s, plan);
     for (int p = 0; p < 4; ++p) {
@@ -521,7 +543,7 @@ int launch_sort(const SortSeg* segs, uint32_t nseg, void* ws, size_t ws_bytes, h
             hipLaunchKernelGGL(k_onesweep<false>, dim3(ntiles), dim3(kSweepThreads), 0, s, descs, nseg, plan, p, lb,
                                ntiles, seg_pre);
     }
-    hipLaunchKernelGGL(k_copy_if_idle, dim3(ntiles), dim3(kThreads), 0, s, descs, nseg, plan);
+    hipLaunchKernelGGL(k_copy_if_idle, dim3(ntiles), dim3(kThreads), 0, s, descs, nseg, plan, tile);
     BITS_CHECK_HIP(hipGetLastError());
     return BITS_OK;
 }

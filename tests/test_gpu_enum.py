@@ -55,7 +55,7 @@ def enumerate_all(b_s, b_e, a_s, a_e, max_pairs=None, status=None, learned=False
     return down(counts), down(offsets), index, down(pa), down(pb)
 
 
-@pytest.mark.parametrize("n,span", [(1, 10), (4095, 1000), (4096, 2**32), (4097, 7), (70_001, 2**24),
+@pytest.mark.parametrize("n,span", [(1, 10), (4095, 1000), (16_384, 2**32), (16_385, 7), (70_001, 2**24),
                                     (300_000, 2**32), (5000, 1)])
 def test_index_is_stable_sort_by_start(n, span):
     """The index is B_S sorted with each interval's input index carried along by

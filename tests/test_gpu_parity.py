@@ -154,9 +154,11 @@ def test_heavy_duplicates_and_clustered_keys():
 
 
 def test_segmented_sort_many_references():
+    """Segments of every size class around the keys-only sort's 20480-key tile
+    (one short of a tile, exactly one, one more, three and a ragged tail)."""
     note("case: segmented sort")
     r = np.random.default_rng(5)
-    sizes = [0, 1, 4095, 4096, 4097, 100_000, 12_345]
+    sizes = [0, 1, 4097, 20_479, 20_480, 20_481, 61_441, 100_000, 12_345]
     sets = []
     for n in sizes:
         a = r.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
