@@ -232,6 +232,33 @@ __device__ __forceinline__ float wave_reduce_scatter(const float (&g)[kNP + 1]) 
     return f[0];
 }
 
+// One training point's contribution to the per-lane partial sums (see
+// wave_grad).  FIRST assigns instead of adding, which gives the same values
+// as adding to zeros without the 50 clears.
+template <bool FIRST>
+__device__ __forceinline__ void add_point(const float (&p)[kNP], float uk, float tk, float scale,
+                                          float (&g)[kNP + 1]) {
+    float pre[16], h[16];
+    float y = p[48];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        pre[q] = fmaf(p[q], uk, p[16 + q]);
+        h[q] = fmaxf(pre[q], 0.0f);
+        y = fmaf(p[32 + q], h[q], y);
+    }
+    const float r = y - tk;
+    const float dy = r * scale;
+    g[kNP] = FIRST ? r * r : fmaf(r, r, g[kNP]);
+    g[48] = FIRST ? dy : g[48] + dy;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const float dh = pre[q] > 0.0f ? dy * p[32 + q] : 0.0f;
+        g[32 + q] = FIRST ? dy * h[q] : fmaf(dy, h[q], g[32 + q]);
+        g[q] = FIRST ? dh * uk : fmaf(dh, uk, g[q]);
+        g[16 + q] = FIRST ? dh : g[16 + q] + dh;
+    }
+}
+
 // Loss gradient of the leaf model over points (u[j], t[j]), j < m: lane l
 // takes points l, l + 64, ... in order.  The per-lane partial sums are the
 // gradients of mean (y - t)^2 with respect to the 49 parameters and, as
@@ -241,31 +268,16 @@ __device__ __forceinline__ float wave_grad(const float (&p)[kNP], const float* u
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const float scale = m ? 2.0f / (float)m : 0.0f;
     float g[kNP + 1];
+    if (__builtin_amdgcn_readfirstlane(m) >= kWave) {   // every lane has a first point (m is wave-uniform)
+        add_point<true>(p, u[lane], t[lane], scale, g);
+#pragma unroll 1
+        for (uint32_t j = lane + kWave; j < m; j += kWave) add_point<false>(p, u[j], t[j], scale, g);
+        return wave_reduce_scatter(g);
+    }
 #pragma unroll
     for (int k = 0; k <= kNP; ++k) g[k] = 0.0f;
 #pragma unroll 1
-    for (uint32_t j = lane; j < m; j += kWave) {
-        const float uk = u[j];
-        float pre[16], h[16];
-        float y = p[48];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            pre[q] = fmaf(p[q], uk, p[16 + q]);
-            h[q] = fmaxf(pre[q], 0.0f);
-            y = fmaf(p[32 + q], h[q], y);
-        }
-        const float r = y - t[j];
-        g[kNP] = fmaf(r, r, g[kNP]);
-        const float dy = r * scale;
-        g[48] += dy;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            g[32 + q] = fmaf(dy, h[q], g[32 + q]);
-            const float dh = pre[q] > 0.0f ? dy * p[32 + q] : 0.0f;
-            g[q] = fmaf(dh, uk, g[q]);
-            g[16 + q] += dh;
-        }
-    }
+    for (uint32_t j = lane; j < m; j += kWave) add_point<false>(p, u[j], t[j], scale, g);
     return wave_reduce_scatter(g);
 }
 
