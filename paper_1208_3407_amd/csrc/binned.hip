@@ -43,11 +43,10 @@ constexpr uint32_t kRegionKeys = 8192;     // merged B_S + B_E keys per region (
 constexpr uint32_t kMargin = 256;          // B_S keys staged past a region's end
 constexpr uint32_t kSliceWords = 12800;    // LDS slice capacity of the search kernel (50 KiB)
 // Bucket tables of the search kernel: a region's coordinate range is cut
-// into at most kBuckets equal power-of-two buckets; word b of a table packs
-// the slice ranks of bucket b's first and last coordinate + 1 (16 bits each:
-// slices hold fewer than 2^16 keys).
+// into at most kBuckets equal power-of-two buckets; word b of a table is the
+// slice rank of bucket b's first coordinate (b = 0 .. buckets, the last one
+// closing the final bucket).
 constexpr uint32_t kBuckets = 1536;
-static_assert(kSliceWords < 65536u, "bucket ranks are 16-bit");
 constexpr uint32_t kBinThreads = 1024;
 constexpr int ILP = 4;   // table entries each binning thread loads before it places them
 // A reference with few regions (a small B) would leave most of the chip idle
@@ -432,6 +431,19 @@ __device__ __forceinline__ void wave_segment_add(uint32_t key, T v, bool valid, 
     if (lane != 0 && kp != key) atomicAdd(&acc[key], 0ull - (unsigned long long)(x - v));
 }
 
+// R[b] = #{K[0..m) < key_lo + b 2^sh} for b = 0 .. nb, K sorted with
+// K[0] >= key_lo.  With F(x) = (x - key_lo) >> sh, the largest b whose
+// coordinate is <= x, key j writes j to the buckets in (F(K[j - 1]), F(K[j])]
+// and a final step j = m fills the rest up to nb: every bucket is written
+// once, in one pass over the keys.
+__device__ void bucket_ranks(const uint32_t* K, uint32_t m, uint32_t key_lo, uint32_t sh, uint32_t nb, uint32_t* R) {
+    for (uint32_t j = threadIdx.x; j <= m; j += blockDim.x) {
+        const uint32_t lo = j == 0 ? 0u : min((K[j - 1] - key_lo) >> sh, nb) + 1u;
+        const uint32_t hi = j == m ? nb : min((K[j] - key_lo) >> sh, nb);
+        for (uint32_t b = lo; b <= hi; ++b) R[b] = j;
+    }
+}
+
 // The placements of one region, counted against slices S = B_S[s_lo, s_lo + ns)
 // and E = B_E[e_lo, e_lo + ne) (in LDS, or in HBM for an oversize region):
 // the workgroup's share [q0, q1) of the region's records.  Each wave takes a
@@ -439,8 +451,9 @@ __device__ __forceinline__ void wave_segment_add(uint32_t key, T v, bool valid, 
 // shuffle (pre[s] = first record of shuffle s), so a wave tracks its shuffle
 // by a forward scan and adds per-shuffle sums with wave_segment_add.
 // Bucket geometry of a region [key_lo, key_hi): bucket of x = (x - key_lo) >> sh.
-// On the LDS path, TS / TE hold word b = rank(v_b) | rank(v_{b+1}) << 16,
-// v_b = key_lo + b 2^sh, the ranks being #{S < v} and #{E < v} in the slices.
+// On the LDS path, TS / TE hold word b = rank(v_b), v_b = key_lo + b 2^sh,
+// the ranks being #{S < v} and #{E < v} in the slices; bucket b's keys are
+// ranks [TS[b], TS[b + 1]).
 struct Buckets {
     const uint32_t* TS;
     const uint32_t* TE;
@@ -465,19 +478,32 @@ __device__ __forceinline__ void bin_count_region(const uint32_t* S, uint32_t ns,
         const uint32_t mid = (sw + hi) >> 1;
         if (pre[mid] <= p0) sw = mid; else hi = mid;
     }
+    // Software pipeline: the record of the next step is loaded before this
+    // step's searches, so a wave has two record loads in flight.  A lane's
+    // shuffle only moves forward, as its record index grows by 64 a step.
+    uint32_t sl = sw;
+    uint2 rn = make_uint2(0u, 0u);
+    if (p0 + lane < p1) {
+        const uint32_t p = (uint32_t)p0 + lane;
+        while (pre[sl + 1] <= p) ++sl;   // ends at sl < nb: p < pre[nb]
+        rn = recs[base[sl] + p];
+    }
     for (uint64_t b = p0; b < p1; b += kWave) {
         const bool valid = b + lane < p1;
-        const uint32_t p = (uint32_t)b + lane;
-        uint32_t sl = sw;
+        const uint32_t slc = sl;
+        const uint2 r = rn;
+        if (b + kWave + lane < p1) {
+            const uint32_t p = (uint32_t)(b + kWave) + lane;
+            while (pre[sl + 1] <= p) ++sl;
+            rn = recs[base[sl] + p];
+        }
         T v = 0;
         if (valid) {
-            while (pre[sl + 1] <= p) ++sl;   // ends at sl < nb: p < pre[nb]
-            const uint2 r = recs[base[sl] + p];
             uint32_t first, last;
             if (LDS && r.y < bk.key_hi) {
                 // every key <= r.y is below key_hi, so inside the slice: the bucket's keys decide
-                const uint32_t w = bk.TS[(r.y - bk.key_lo) >> bk.sh], lo = w & 0xFFFFu;
-                first = s_lo + lo + rank_in<false>(S + lo, (w >> 16) - lo, r.y);
+                const uint32_t b = (r.y - bk.key_lo) >> bk.sh, lo = bk.TS[b];
+                first = s_lo + lo + rank_in<false>(S + lo, bk.TS[b + 1] - lo, r.y);
             } else if (r.y == 0xFFFFFFFFu) {
                 first = n;
             } else {
@@ -485,15 +511,14 @@ __device__ __forceinline__ void bin_count_region(const uint32_t* S, uint32_t ns,
                 first = (c == ns && s_end < n) ? gallop_le(bs, n, s_end, r.y) : s_lo + c;
             }
             if (LDS) {   // key_lo <= r.x < key_hi: the start lies in the region
-                const uint32_t w = bk.TE[(r.x - bk.key_lo) >> bk.sh], lo = w & 0xFFFFu;
-                last = e_lo + lo + rank_in<true>(E + lo, (w >> 16) - lo, r.x);
+                const uint32_t b = (r.x - bk.key_lo) >> bk.sh, lo = bk.TE[b];
+                last = e_lo + lo + rank_in<true>(E + lo, bk.TE[b + 1] - lo, r.x);
             } else {
                 last = e_lo + rank_in<true>(E, ne, r.x);
             }
             v = (T)(first - last);
         }
-        wave_segment_add<T>(valid ? sl : 0xFFFFFFFFu, v, valid, acc);
-        sw = __builtin_amdgcn_readlane(sl, kWave - 1);
+        wave_segment_add<T>(valid ? slc : 0xFFFFFFFFu, v, valid, acc);
     }
 }
 
@@ -508,7 +533,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_search(
     const uint32_t* __restrict__ seg_cnt, uint32_t nreg_max, uint32_t nb, const uint2* __restrict__ recs,
     uint64_t na, uint32_t splits, unsigned long long* __restrict__ partial) {
     __shared__ uint32_t slice[kSliceWords];
-    __shared__ uint32_t tabs[2 * kBuckets];
+    __shared__ uint32_t tabs[2 * (kBuckets + 1)];
     __shared__ uint32_t pre[BITS_MC_BIN_MAX_BATCH + 1];
     __shared__ uint32_t base[BITS_MC_BIN_MAX_BATCH];
     __shared__ unsigned long long acc[BITS_MC_BIN_MAX_BATCH];
@@ -549,7 +574,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_search(
     const uint32_t eo = ns;   // E's first word
     const bool in_lds = (uint64_t)ns + ne <= kSliceWords;
     // buckets: the least power-of-two width that cuts [key_lo, key_hi) into at most kBuckets
-    Buckets bk{tabs, tabs + kBuckets, d0.key_lo, d1.key_lo, 0u};
+    Buckets bk{tabs, tabs + kBuckets + 1, d0.key_lo, d1.key_lo, 0u};
     const uint32_t span = bk.key_hi - bk.key_lo;   // > 0: a region holds at least one cell
     while (((span - 1u) >> bk.sh) >= kBuckets) ++bk.sh;
     const uint32_t nbk = ((span - 1u) >> bk.sh) + 1u;
@@ -557,15 +582,8 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_search(
         for (uint32_t j = threadIdx.x; j < ns; j += blockDim.x) slice[j] = bs[s_lo + j];
         for (uint32_t j = threadIdx.x; j < ne; j += blockDim.x) slice[eo + j] = be[e_lo + j];
         __syncthreads();
-        for (uint32_t b = threadIdx.x; b < nbk; b += blockDim.x) {
-            const uint64_t v0 = (uint64_t)bk.key_lo + ((uint64_t)b << bk.sh), v1 = v0 + (1ull << bk.sh);
-            const uint32_t s0 = v0 > 0xFFFFFFFFull ? ns : rank_in<true>(slice, ns, (uint32_t)v0);
-            const uint32_t s1 = v1 > 0xFFFFFFFFull ? ns : rank_in<true>(slice, ns, (uint32_t)v1);
-            const uint32_t e0 = v0 > 0xFFFFFFFFull ? ne : rank_in<true>(slice + eo, ne, (uint32_t)v0);
-            const uint32_t e1 = v1 > 0xFFFFFFFFull ? ne : rank_in<true>(slice + eo, ne, (uint32_t)v1);
-            tabs[b] = s0 | (s1 << 16);
-            tabs[kBuckets + b] = e0 | (e1 << 16);
-        }
+        bucket_ranks(slice, ns, bk.key_lo, bk.sh, nbk, tabs);
+        bucket_ranks(slice + eo, ne, bk.key_lo, bk.sh, nbk, tabs + kBuckets + 1);
     }
     __syncthreads();
     // this workgroup's share of the region's records
