@@ -211,6 +211,40 @@ __global__ void __launch_bounds__(256) k_bin_pack(const uint32_t* __restrict__ s
         packed[p] = make_uint2(idx[p], span[p] ? len[p] : 0u);
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave, moving data between lanes
+// with DPP only (no LDS instruction, so it does not queue behind the
+// bisections): four row_shr steps (1, 2, 4, 8) build the prefix inside each
+// row of 16 lanes, then row_bcast:15 adds row 0's total to row 1 and row 2's
+// to row 3, and row_bcast:31 adds the total of rows 0-1 to rows 2 and 3.
+// Lanes whose source lies outside the row, and rows the row mask leaves out,
+// receive 0 (the `old` operand), so every step is a plain add.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_in0(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void scan_step(uint32_t& x) {
+    x += dpp_in0<CTRL, ROWS>(x);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void scan_step(uint64_t& x) {
+    const uint32_t lo = dpp_in0<CTRL, ROWS>((uint32_t)x), hi = dpp_in0<CTRL, ROWS>((uint32_t)(x >> 32));
+    x += ((uint64_t)hi << 32) | lo;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T x) {
+    scan_step<0x111, 0xF>(x);   // row_shr:1
+    scan_step<0x112, 0xF>(x);   // row_shr:2
+    scan_step<0x114, 0xF>(x);   // row_shr:4
+    scan_step<0x118, 0xF>(x);   // row_shr:8
+    scan_step<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
+    scan_step<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
 // Staged binning (second sweep): chromosomes with kStageMinRegions..kStageRegions
 // regions; kStageRecs records per chunk, so that the workgroup's LDS (about 76 KB)
 // still lets two workgroups share a CU.
@@ -306,9 +340,16 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_bin_place(
         return;
     }
     // staged: chunks of kStageRecs table entries are placed, counting-sorted by region in
-    // LDS, and written out in region runs
+    // LDS, and written out in region runs.  Thread t < nw2 owns regions 2t and 2t + 1
+    // (counter word t) for the whole loop.  During a chunk, hs[r] holds region r's cursor
+    // minus the offset of r's run in the chunk, so the chunk's record j goes to
+    // g0 + hs[r] + j; the next chunk's scan adds back the end of that run (kept in the
+    // owner's registers) to get the cursor again.  Four barriers a chunk: the next
+    // chunk's ranking touches only the counters, so it may overlap this write-out.
     const uint32_t nw2 = (nr + 1) >> 1;
-    for (uint32_t j = threadIdx.x; j < nw2; j += blockDim.x) cc[j] = 0u;
+    const bool owner = threadIdx.x < nw2;
+    if (owner) cc[threadIdx.x] = 0u;
+    uint32_t end0 = 0u, end1 = 0u;   // the owner's run ends in the previous chunk
     __syncthreads();
     for (uint32_t cb = g0; cb < g1; cb += kStageRecs) {
         const uint32_t ce = min(g1, cb + kStageRecs);
@@ -329,18 +370,15 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_bin_place(
             st_[u] = st;
             key_[u] = (lr << 16) | ((old >> sft) & 0xFFFFu);
         }
-        __syncthreads();
-        // exclusive offsets of the chunk's region counts (two per word) into co
+        __syncthreads();   // counts complete; the previous chunk is written out
+        // exclusive offsets of the chunk's region counts (two per word) into co, and the
+        // owners' cursors turned into this chunk's deltas
         {
-            const uint32_t wv = threadIdx.x < nw2 ? cc[threadIdx.x] : 0u;
+            const uint32_t wv = owner ? cc[threadIdx.x] : 0u;
+            if (owner) cc[threadIdx.x] = 0u;   // ready for the next chunk
             const uint32_t a0 = wv & 0xFFFFu, a1 = wv >> 16, tsum = a0 + a1;
             const uint32_t lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-            uint32_t x = tsum;
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const uint32_t y = __shfl_up(x, o);
-                if (lane >= (uint32_t)o) x += y;
-            }
+            const uint32_t x = wave_inclusive_scan<uint32_t>(tsum);
             if (lane == kWave - 1) wsum[w] = x;
             __syncthreads();
             uint32_t pre = 0, tot = 0;
@@ -349,7 +387,16 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_bin_place(
                 tot += wsum[j];
             }
             pre += x - tsum;
-            if (threadIdx.x < nw2) co[threadIdx.x] = pre | ((pre + a0) << 16);
+            if (owner) {
+                const uint32_t r0 = 2u * threadIdx.x, lo1 = pre + a0;
+                co[threadIdx.x] = pre | (lo1 << 16);
+                hs[r0] = hs[r0] + end0 - pre;
+                end0 = lo1;
+                if (r0 + 1u < nr) {
+                    hs[r0 + 1u] = hs[r0 + 1u] + end1 - lo1;
+                    end1 = lo1 + a1;
+                }
+            }
             if (threadIdx.x == 0) staged_total = tot;
         }
         __syncthreads();
@@ -364,53 +411,9 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_bin_place(
         for (uint32_t j = threadIdx.x; j < tot; j += blockDim.x) {
             const uint2 rec = stage[j];
             const uint32_t lr = cr[(rec.x - ok) >> sh];
-            out[g0 + hs[lr] + (j - half16(co, lr))] = rec;
+            out[g0 + hs[lr] + j] = rec;
         }
-        __syncthreads();
-        // advance the cursors by the chunk's counts and clear the counters (each thread its
-        // own counter words)
-        for (uint32_t j = threadIdx.x; j < nw2; j += blockDim.x) {
-            const uint32_t c = cc[j];
-            hs[2 * j] += c & 0xFFFFu;
-            if (2 * j + 1 < nr) hs[2 * j + 1] += c >> 16;
-            cc[j] = 0u;
-        }
-        __syncthreads();
     }
-}
-
-// Inclusive prefix sum over the 64 lanes of a wave, moving data between lanes
-// with DPP only (no LDS instruction, so it does not queue behind the
-// bisections): four row_shr steps (1, 2, 4, 8) build the prefix inside each
-// row of 16 lanes, then row_bcast:15 adds row 0's total to row 1 and row 2's
-// to row 3, and row_bcast:31 adds the total of rows 0-1 to rows 2 and 3.
-// Lanes whose source lies outside the row, and rows the row mask leaves out,
-// receive 0 (the `old` operand), so every step is a plain add.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ uint32_t dpp_in0(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
-}
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ void scan_step(uint32_t& x) {
-    x += dpp_in0<CTRL, ROWS>(x);
-}
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ void scan_step(uint64_t& x) {
-    const uint32_t lo = dpp_in0<CTRL, ROWS>((uint32_t)x), hi = dpp_in0<CTRL, ROWS>((uint32_t)(x >> 32));
-    x += ((uint64_t)hi << 32) | lo;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_inclusive_scan(T x) {
-    scan_step<0x111, 0xF>(x);   // row_shr:1
-    scan_step<0x112, 0xF>(x);   // row_shr:2
-    scan_step<0x114, 0xF>(x);   // row_shr:4
-    scan_step<0x118, 0xF>(x);   // row_shr:8
-    scan_step<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
-    scan_step<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
-    return x;
 }
 
 // Wave-level segmented sum: lanes carry (key, value) with the keys of the

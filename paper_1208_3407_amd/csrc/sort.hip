@@ -159,12 +159,22 @@ __global__ void __launch_bounds__(kThreads) k_hist_all(const SegDesc* __restrict
         const uint32_t begin = (t - d.tile0) * tile;
         const uint32_t cnt = min(tile, d.n - begin);
         const uint32_t* src = d.in + begin;
-        for (uint32_t k = threadIdx.x; k < cnt; k += kThreads) {
-            const uint32_t key = src[k];
-            atomicAdd(&h[0][key & 255u], 1u);
-            atomicAdd(&h[1][(key >> 8) & 255u], 1u);
-            atomicAdd(&h[2][(key >> 16) & 255u], 1u);
-            atomicAdd(&h[3][key >> 24], 1u);
+        // four independent loads per thread in flight, then their counts
+        for (uint32_t k0 = threadIdx.x; k0 < cnt; k0 += 4 * kThreads) {
+            uint32_t key[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t k = k0 + (uint32_t)u * kThreads;
+                key[u] = src[min(k, cnt - 1u)];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (k0 + (uint32_t)u * kThreads >= cnt) break;
+                atomicAdd(&h[0][key[u] & 255u], 1u);
+                atomicAdd(&h[1][(key[u] >> 8) & 255u], 1u);
+                atomicAdd(&h[2][(key[u] >> 16) & 255u], 1u);
+                atomicAdd(&h[3][key[u] >> 24], 1u);
+            }
         }
     }
     __syncthreads();
