@@ -95,6 +95,22 @@ __device__ __forceinline__ uint32_t rank_in(const uint32_t* K, uint32_t m, uint3
     return base + (STRICT ? (k < x) : (k <= x));
 }
 
+// rank_in for the few keys of one bucket: no early exit for m = 0 (K[0] is
+// then still read, at most one word past the slices, and ignored), so that
+// the lanes of a wave do not branch around each other.
+template <bool STRICT>
+__device__ __forceinline__ uint32_t rank_bucket(const uint32_t* K, uint32_t m, uint32_t x) {
+    uint32_t base = 0, len = m;
+    while (len > 1) {
+        const uint32_t half = len >> 1;
+        const uint32_t k = K[base + half];
+        if (STRICT ? (k < x) : (k <= x)) base += half;
+        len -= half;
+    }
+    const uint32_t k = K[base];
+    return base + ((m != 0u) & (STRICT ? (k < x) : (k <= x)));
+}
+
 // #{bs <= x} over the whole array, given that bs[j - 1] <= x (j >= 1) or j = 0.
 __device__ uint32_t gallop_le(const uint32_t* __restrict__ bs, uint32_t n, uint32_t j, uint32_t x) {
     uint32_t lo = j, hi = n;
@@ -506,7 +522,7 @@ __device__ __forceinline__ void bin_count_region(const uint32_t* S, uint32_t ns,
             if (LDS && r.y < bk.key_hi) {
                 // every key <= r.y is below key_hi, so inside the slice: the bucket's keys decide
                 const uint32_t b = (r.y - bk.key_lo) >> bk.sh, lo = bk.TS[b];
-                first = s_lo + lo + rank_in<false>(S + lo, bk.TS[b + 1] - lo, r.y);
+                first = s_lo + lo + rank_bucket<false>(S + lo, bk.TS[b + 1] - lo, r.y);
             } else if (r.y == 0xFFFFFFFFu) {
                 first = n;
             } else {
@@ -515,7 +531,7 @@ __device__ __forceinline__ void bin_count_region(const uint32_t* S, uint32_t ns,
             }
             if (LDS) {   // key_lo <= r.x < key_hi: the start lies in the region
                 const uint32_t b = (r.x - bk.key_lo) >> bk.sh, lo = bk.TE[b];
-                last = e_lo + lo + rank_in<true>(E + lo, bk.TE[b + 1] - lo, r.x);
+                last = e_lo + lo + rank_bucket<true>(E + lo, bk.TE[b + 1] - lo, r.x);
             } else {
                 last = e_lo + rank_in<true>(E, ne, r.x);
             }
@@ -535,7 +551,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_search(
     const RegionDesc* __restrict__ desc, const uint64_t* __restrict__ nreg_p, const uint32_t* __restrict__ seg_start,
     const uint32_t* __restrict__ seg_cnt, uint32_t nreg_max, uint32_t nb, const uint2* __restrict__ recs,
     uint64_t na, uint32_t splits, unsigned long long* __restrict__ partial) {
-    __shared__ uint32_t slice[kSliceWords];
+    __shared__ uint32_t slice[kSliceWords + 1];   // + 1: the word an empty last bucket reads
     __shared__ uint32_t tabs[2 * (kBuckets + 1)];
     __shared__ uint32_t pre[BITS_MC_BIN_MAX_BATCH + 1];
     __shared__ uint32_t base[BITS_MC_BIN_MAX_BATCH];
