@@ -68,7 +68,7 @@ typedef enum bits_status {
 /* Search path selection for a call (bits_launch.path). */
 #define BITS_PATH_AUTO    0u      /* learned index if the reference has one, else plain */
 #define BITS_PATH_PLAIN   1u      /* LDS Eytzinger top tree + bisection in HBM */
-#define BITS_PATH_LEARNED 2u      /* learned CDF index + windowed search (needs learned ref) */
+#define BITS_PATH_LEARNED 2u      /* learned CDF index + error-window search over the line heads (needs learned ref) */
 #define BITS_PATH_TIERED  3u      /* counting only: LDS top tree, then bisection over the
                                      32-key node tier (the line heads), then one 128-byte line;
                                      no model (the index the learned path is measured against) */

@@ -373,9 +373,9 @@ __device__ __forceinline__ void leaf_stage(const SearchArgs& sa, uint32_t* scr, 
     }
 }
 
-// Windowed learned search, leaf part: either the resolved rank (base,
-// win = false) or the error window [wl, wr] around the prediction and the
-// line to probe first.  Must be called by all 64 lanes.
+// Learned search, leaf part: either the resolved rank (base, win = false) or
+// the recorded error window [wl, wr] around the prediction (and the line
+// holding the prediction).  Must be called by all 64 lanes.
 template <int NC>
 __device__ __forceinline__ void learned_windows(const SearchArgs& sa, uint32_t* scr, const uint32_t (&x)[NC],
                                                 uint32_t (&base)[NC], uint32_t (&len)[NC], uint32_t (&wl)[NC],
@@ -398,79 +398,6 @@ __device__ __forceinline__ void learned_windows(const SearchArgs& sa, uint32_t* 
             base[c] = wl[c];
             if (wr[c] > wl[c]) ln[c] = min(max(pred[c], wl[c]), wr[c] - 1u) >> 5;
         }
-    }
-}
-
-template <int QPL>
-__device__ __forceinline__ void icount_learned(const SearchArgs& sa, uint32_t* scr, const uint32_t (&as)[QPL],
-                                               const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL],
-                                               uint32_t (&fst)[QPL]) {
-    constexpr int NC = 2 * QPL;
-    uint32_t x[NC], base[NC], len[NC], wl[NC], wr[NC], rlo[NC], rhi[NC], ln[NC], pc[NC];
-    bool win[NC];
-#pragma unroll
-    for (int q = 0; q < QPL; ++q) {
-        x[2 * q] = ae[q] + 1u;
-        x[2 * q + 1] = as[q];
-    }
-    learned_windows<NC>(sa, scr, x, base, len, wl, wr, rlo, rhi, ln, win);
-    uint32_t lw[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) lw[c] = ln[c] == kNoLine ? kNoLine : ln[c] * 32u;
-    probe_lines<NC, true>(sa.bs, sa.be, lw, x, pc, scr);
-    bool exact[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        exact[c] = false;
-        if (ln[c] == kNoLine) continue;
-        const uint32_t l0 = ln[c] * 32u, l1 = min(l0 + 32u, sa.n);
-        if ((pc[c] == 0 && l0 < rlo[c]) || (pc[c] >= l1 - l0 && l1 > rhi[c])) {
-            // impossible for a consistent index (the lower bound lies in
-            // [rlo, rhi]); bisect the leaf's whole range instead
-            wl[c] = rlo[c];
-            wr[c] = rhi[c];
-            base[c] = rlo[c];
-            len[c] = rhi[c] - rlo[c];
-        } else if (pc[c] > 0 && l0 + pc[c] < l1) {
-            base[c] = l0 + pc[c];        // the global lower bound: K[l0+pc-1] < x <= K[l0+pc]
-            exact[c] = true;
-        } else if (pc[c] == 0) {
-            // lower bound <= l0 (K[l0] >= x); the line may start left of the
-            // window, which then widens to it (l0 >= rlo holds here because
-            // the lower bound is >= rlo)
-            wl[c] = min(wl[c], l0);
-            base[c] = wl[c];
-            len[c] = l0 - wl[c];
-        } else {
-            // lower bound >= l1 (every key of the line < x); symmetric
-            wr[c] = max(wr[c], l1);
-            base[c] = l1;
-            len[c] = wr[c] - l1;
-        }
-    }
-    bisect_multi<NC>(sa.bs, sa.be, base, len, x, 0u);
-    bool any_fb = false;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        if (!win[c] || exact[c]) continue;
-        const uint32_t* K = (c & 1) ? sa.be : sa.bs;
-        const uint32_t r = base[c];
-        bool ok = true;
-        if (r == wl[c] && wl[c] != rlo[c]) ok = ld_key<true>(K + wl[c] - 1) < x[c];
-        if (r == wr[c] && wr[c] != rhi[c]) ok = ok && (ld_key<true>(K + wr[c]) >= x[c]);
-        if (!ok) {
-            base[c] = rlo[c];
-            len[c] = rhi[c] - rlo[c];
-            any_fb = true;
-            atomicAdd(sa.fallbacks, 1ull);
-        }
-    }
-    if (any_fb) bisect_multi<NC>(sa.bs, sa.be, base, len, x, 0u);
-#pragma unroll
-    for (int q = 0; q < QPL; ++q) {
-        const uint32_t first = (ae[q] == 0xFFFFFFFFu) ? sa.n : base[2 * q];
-        cnt[q] = first - base[2 * q + 1];
-        fst[q] = first;
     }
 }
 
@@ -516,6 +443,70 @@ enum : uint32_t { kHeadHit = 0, kHeadLeft = 1, kHeadRight = 2 };
 __device__ __forceinline__ uint32_t head_outcome(uint32_t w, uint32_t cnt) {
     if (cnt >= kHeadWin) return kHeadRight;
     return (cnt == 0u && w != 0u) ? kHeadLeft : kHeadHit;
+}
+
+// Learned count: the leaf's recorded error window [wl, wr] holds the lower
+// bound r = #{K < x}, so j = #{H < x} = ceil(r / 32) over the line heads
+// (H[j] = K[32 j], kept in L2 / the Infinity Cache) lies in [ceil(wl / 32),
+// ceil(wr / 32)].  One cooperative probe of the kHeadWin heads starting at
+// or below ceil(wl / 32) - 1 resolves j when that range fits in the probe,
+// else the heads of the leaf's whole range [rlo, rhi] are bisected; a probe
+// whose count shows that j left the window (the model erred past its
+// recorded error) falls back to that bisection too, and is counted.  One
+// cooperative probe of line j - 1 then gives r (r = 0 when j = 0).  Must be
+// called by all 64 lanes.
+template <int QPL>
+__device__ __forceinline__ void icount_learned(const SearchArgs& sa, uint32_t* scr, const uint32_t (&as)[QPL],
+                                               const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL],
+                                               uint32_t (&fst)[QPL]) {
+    constexpr int NC = 2 * QPL;
+    uint32_t x[NC], base[NC], len[NC], wl[NC], wr[NC], rlo[NC], rhi[NC], ln[NC];
+    bool win[NC];
+#pragma unroll
+    for (int q = 0; q < QPL; ++q) {
+        x[2 * q] = ae[q] + 1u;
+        x[2 * q + 1] = as[q];
+    }
+    learned_windows<NC>(sa, scr, x, base, len, wl, wr, rlo, rhi, ln, win);
+    const uint32_t m = (sa.n + 31u) >> 5;     // heads in use
+    uint32_t w[NC], pc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const uint32_t jlo = min((wl[c] + 31u) >> 5, m), jhi = min((wr[c] + 31u) >> 5, m);
+        const uint32_t w0 = (jlo > 0u ? jlo - 1u : 0u) & ~(kHeadAlign - 1u);
+        w[c] = (win[c] && jhi < w0 + kHeadWin) ? w0 : kNoLine;
+    }
+    probe_lines<NC, false, kHeadWin, kHeadLanes>(sa.hs, sa.he, w, x, pc, scr);
+    uint32_t j[NC], jl[NC];
+    bool again = false;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        j[c] = 0u;
+        jl[c] = 0u;
+        if (!win[c]) continue;
+        if (w[c] != kNoLine && head_outcome(w[c], pc[c]) == kHeadHit) {
+            j[c] = w[c] + pc[c];
+            continue;
+        }
+        if (w[c] != kNoLine) atomicAdd(sa.fallbacks, 1ull);   // the window missed
+        j[c] = min((rlo[c] + 31u) >> 5, m);
+        jl[c] = min((rhi[c] + 31u) >> 5, m) - j[c];
+        again = true;
+    }
+    if (__ballot(again)) bisect_multi<NC>(sa.hs, sa.he, j, jl, x, 32u);
+    uint32_t dw[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) dw[c] = (win[c] && j[c] != 0u) ? (min(j[c], m) - 1u) * 32u : kNoLine;
+    probe_lines<NC, true>(sa.bs, sa.be, dw, x, pc, scr);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        if (win[c]) base[c] = dw[c] == kNoLine ? 0u : dw[c] + pc[c];
+#pragma unroll
+    for (int q = 0; q < QPL; ++q) {
+        const uint32_t first = (ae[q] == 0xFFFFFFFFu) ? sa.n : base[2 * q];
+        cnt[q] = first - base[2 * q + 1];
+        fst[q] = first;
+    }
 }
 
 template <int QPL>
@@ -657,7 +648,7 @@ __device__ __forceinline__ void icount(const SearchArgs& sa, uint32_t* lds, cons
 // coalesced.  Totals: uint64 wave sum, one atomic per wave.
 
 // MODE: kModePlain (LDS tree + bisection), kModeLearned (learned index,
-// windowed line probe) or kModeTiered (LDS tree + line-head tier + one line).
+// error-window head probe + one line) or kModeTiered (LDS tree + line-head tier + one line).
 template <int QPL, int MODE>
 BITS_SEARCH_KERNEL k_count(SearchArgs sa, const uint32_t* __restrict__ a_start,
                                                 const uint32_t* __restrict__ a_end, uint64_t na,
@@ -1284,7 +1275,7 @@ __global__ void k_project(ChromTab ct, const uint32_t* __restrict__ chrom, const
 // same XCD (hardware dispatches workgroups round-robin over the 8 XCDs), so
 // an XCD's L2 sees few distinct references (and, on the learned path, their
 // leaf records).  LEARNED searches every pair through the reference's learned
-// index (leaf model, windowed line probe), with the per-wave scratch in LDS.
+// index (leaf model, error-window head probe, one line), with the per-wave scratch in LDS.
 template <int QPL, bool LEARNED>
 __global__ void __launch_bounds__(1024)
     k_batch(const BatchRef* __restrict__ refs, const BatchQuery* __restrict__ qs, const BatchItem* __restrict__ items,
