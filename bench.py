@@ -421,42 +421,49 @@ def main():
         lp_tiered = cached_autotune("tiered|" + tag, lambda: bits.bits_autotune_count(ref, a_s, a_e, 3))
         lp_mc = tune_mc(bits, ref, a_s[:N_MC], a_e[:N_MC], lengths, mc_ws)
 
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-
-    def step(record):
+    def step(ev=None):
         a_s, a_e = bits.bits_project(lengths, *dA)
         b_s, b_e = bits.bits_project(lengths, *dB)
-        if record:
+        if ev:
             ev[0].record()
         bits.bits_sort_ref(b_s, b_e, learned=True, train=train, ref=ref, workspace=ws)
-        if record:
+        if ev:
             ev[1].record()
         bits.bits_count_per_query(ref, a_s, a_e, launch=lp_learned, counts=counts, total=total)
-        if record:
+        if ev:
             ev[2].record()
         bits.bits_mc_binned(ref, a_s[:N_MC], a_e[:N_MC], lengths, MC_SEED, 0, N_SHUF, batch=MC_BATCH,
                             launch=lp_mc, workspace=bin_ws, out=mc_out)
-        if record:
+        if ev:
             ev[3].record()
         return a_s, a_e
 
     for _ in range(args.warmup):
-        step(False)
+        step()
     torch.cuda.synchronize()
     phase = {"setup_ms": [], "count_ms": [], "mc_ms": []}
     stages = {"place": [], "search": [], "reduce": []}
+    # The timed steps run back to back with no host wait between them (events only); the
+    # phase times are read once the last step has finished.
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     bits.bits_mc_binned_timing(True)    # HIP events around the binned kernels, on the stream they run on
     t_start = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
-        ev[3].synchronize()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    for ev in evs:
         phase["setup_ms"].append(ev[0].elapsed_time(ev[1]))
         phase["count_ms"].append(ev[1].elapsed_time(ev[2]))
         phase["mc_ms"].append(ev[2].elapsed_time(ev[3]))
+    # the binned kernels' stage times: the last timed step, and two more steps after the timed region
+    for k, v in bits.bits_mc_binned_stage_ms().items():
+        stages[k].append(v)
+    for _ in range(2):
+        step()
+        torch.cuda.synchronize()
         for k, v in bits.bits_mc_binned_stage_ms().items():
             stages[k].append(v)
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
     bits.bits_mc_binned_timing(False)
     ms_per_step = t_total * 1e3 / args.steps
     evals = N_A + N_SHUF * N_MC
