@@ -113,6 +113,29 @@ def test_binned_more_regions_than_staging_holds():
     check(L, a_s, a_e, b_s, b_e, 8, 0, 4, 4, against_pvalue=False)
 
 
+def test_binned_bucket_edges():
+    """Keys in tight clusters separated by wide gaps (most buckets of a region empty, a few
+    holding runs of equal keys) and queries whose starts and ends sit on keys, one before
+    and one after them: the bucket tables' edges and the empty-bucket reads."""
+    note("case: binned bucket edges")
+    r = np.random.default_rng(31)
+    L = np.array([30_000_000, 7_000_000], np.uint32)
+    centres = np.sort(r.integers(0, 36_900_000, 400))
+    b_s = np.concatenate([np.repeat(centres, r.integers(1, 40, len(centres))),
+                          r.integers(0, 36_990_000, 5000)]).astype(np.int64)
+    b_s = np.clip(b_s + r.integers(-3, 4, len(b_s)), 0, 36_990_000).astype(np.uint32)
+    b_e = b_s + r.integers(0, 6, len(b_s)).astype(np.uint32)
+    pick = r.integers(0, len(b_s), 4000)
+    a_s = (b_s[pick].astype(np.int64) + r.integers(-1, 2, len(pick))).clip(0, 36_999_000).astype(np.uint32)
+    a_e = (b_e[pick].astype(np.int64) + r.integers(-1, 2, len(pick)))
+    a_e = np.maximum(a_e, a_s).astype(np.uint32)
+    # keep every query inside its chromosome
+    off = np.array([0, 30_000_000, 37_000_000], np.int64)
+    c = np.searchsorted(off, a_s, side="right") - 1
+    a_e = np.minimum(a_e.astype(np.int64), off[c + 1] - 1).astype(np.uint32)
+    check(L, a_s, a_e, b_s, b_e, 13, 0, 24, 8)
+
+
 def test_binned_oversize_region_and_empty_chromosomes():
     """Empty chromosomes between non-empty ones, 12,000 intervals of B on one
     coordinate (a region too large for LDS, searched in HBM), B keys past the
