@@ -90,6 +90,30 @@ def test_genome_scale_shapes_plain_and_learned(na, nb):
     assert bits.bits_get_status(ref) == 0
 
 
+@pytest.mark.parametrize("n", [1, 31, 32, 33, 63, 64, 65, 1000, 4097, 70_001])
+def test_learned_count_head_edges(n):
+    """The learned count's head search at line and array edges: references of sizes around
+    the 32-key line, queries whose ends sit on keys, one before and one after them, at
+    coordinate 0 and at 2^32 - 1, against the oracle; trained and untrained models."""
+    note("case: learned head edges n=%d" % n)
+    r = np.random.default_rng(n)
+    b_s = np.sort(r.integers(0, 2**32 - 2, n, dtype=np.uint64)).astype(np.uint32)
+    b_s[: n // 3] = b_s[0]                       # a run of equal keys at the start
+    b_e = np.minimum(b_s.astype(np.uint64) + r.integers(0, 1000, n), 2**32 - 2).astype(np.uint32)
+    pick = r.integers(0, n, 3000)
+    a_s = np.concatenate([b_e[pick].astype(np.int64) + r.integers(-1, 2, len(pick)), [0, 0, 2**32 - 2]])
+    a_s = a_s.clip(0, 2**32 - 2).astype(np.uint32)
+    a_e = np.concatenate([b_s[pick].astype(np.int64) + r.integers(-1, 2, len(pick)), [0, 2**32 - 2, 2**32 - 2]])
+    a_e = np.maximum(a_e.clip(0, 2**32 - 2), a_s).astype(np.uint32)
+    exp, tot = oracle.count_sorted(np.sort(b_s), np.sort(b_e), a_s, a_e)
+    for epochs in (0, 40):
+        ref = bits.bits_sort_ref(up(b_s), up(b_e), learned=True, train={"epochs": epochs})
+        c, t = bits.bits_count_per_query(ref, up(a_s), up(a_e), launch={"path": 2})
+        assert np.array_equal(down(c), exp), (n, epochs)
+        assert int(down(t)[0]) == tot
+        assert bits.bits_get_status(ref) == 0
+
+
 def test_edge_cases():
     note("case: edge cases")
     z = torch.empty(0, dtype=torch.uint32, device=DEV)
