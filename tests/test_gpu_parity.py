@@ -177,6 +177,31 @@ def test_heavy_duplicates_and_clustered_keys():
         assert int(down(t)[0]) == tot
 
 
+@pytest.mark.parametrize("kind", ["descending", "top_byte_only", "low_byte_only", "few_distinct"])
+def test_sort_key_patterns(kind):
+    """The keys-only radix sort on patterns that stress single digit passes: a descending
+    run, keys that differ only in the top or only in the low byte (the other passes are
+    skipped), and a few distinct values (long equal-digit runs in every tile), at
+    3 x 20480 + 5 keys, against numpy."""
+    note("case: sort pattern %s" % kind)
+    n = 3 * 20480 + 5
+    r = np.random.default_rng(7)
+    if kind == "descending":
+        k = np.arange(n, 0, -1, dtype=np.uint64) * 65_537 % 2**32
+    elif kind == "top_byte_only":
+        k = (r.integers(0, 256, n, dtype=np.uint64) << 24) | 0x00ABCDEF
+    elif kind == "low_byte_only":
+        k = r.integers(0, 256, n, dtype=np.uint64) | 0x12345600
+    else:
+        k = r.choice(np.array([0, 1, 2**31, 2**32 - 1], np.uint64), n)
+    k = k.astype(np.uint32)
+    e = np.roll(k, 17)
+    ref = bits.bits_sort_ref(up(k), up(e))
+    assert np.array_equal(down(ref.sorted_starts()), np.sort(k))
+    assert np.array_equal(down(ref.sorted_ends()), np.sort(e))
+    assert bits.bits_get_status(ref) == 0
+
+
 def test_segmented_sort_many_references():
     """Segments of every size class around the keys-only sort's 20480-key tile
     (one short of a tile, exactly one, one more, three and a ragged tail)."""
