@@ -60,7 +60,7 @@ LDS_PEAK_GBS = 128 * 256 * 2.4
 VALU_PEAK_G = 256 * 2.4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_bin_w4.json")
 # launch shapes the autotuner picked on MI355X for this workload (used with --no-autotune)
-RECORDED_LEARNED = {"block": 256, "qpl": 1, "depth": 0, "grid": 0, "path": 2}
+RECORDED_LEARNED = {"block": 512, "qpl": 1, "depth": 0, "grid": 0, "path": 2}
 RECORDED_PLAIN = {"block": 256, "qpl": 1, "depth": 13, "grid": 0, "path": 1}
 RECORDED_TIERED = {"block": 256, "qpl": 1, "depth": 13, "grid": 0, "path": 3}
 RECORDED_MC = {"block": 1024, "qpl": 1, "depth": 0, "grid": 0, "path": 2}
