@@ -374,20 +374,17 @@ __device__ __forceinline__ void leaf_stage(const SearchArgs& sa, uint32_t* scr, 
 }
 
 // Learned search, leaf part: either the resolved rank (base, win = false) or
-// the recorded error window [wl, wr] around the prediction (and the line
-// holding the prediction).  Must be called by all 64 lanes.
+// the recorded error window [wl, wr] around the prediction (base = wl).  Must
+// be called by all 64 lanes.
 template <int NC>
 __device__ __forceinline__ void learned_windows(const SearchArgs& sa, uint32_t* scr, const uint32_t (&x)[NC],
-                                                uint32_t (&base)[NC], uint32_t (&len)[NC], uint32_t (&wl)[NC],
-                                                uint32_t (&wr)[NC], uint32_t (&rlo)[NC], uint32_t (&rhi)[NC],
-                                                uint32_t (&ln)[NC], bool (&win)[NC]) {
+                                                uint32_t (&base)[NC], uint32_t (&wl)[NC], uint32_t (&wr)[NC],
+                                                uint32_t (&rlo)[NC], uint32_t (&rhi)[NC], bool (&win)[NC]) {
     uint32_t pred[NC], err[NC];
     leaf_stage<NC>(sa, scr, x, rlo, rhi, pred, err, win);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         base[c] = pred[c];
-        len[c] = 0;
-        ln[c] = kNoLine;
         wl[c] = wr[c] = 0;
         if (win[c]) {
             const int32_t p = (int32_t)pred[c];
@@ -396,7 +393,6 @@ __device__ __forceinline__ void learned_windows(const SearchArgs& sa, uint32_t* 
             wr[c] = (uint32_t)min(hi, (int32_t)rhi[c]);
             if (wr[c] < wl[c]) wr[c] = wl[c];
             base[c] = wl[c];
-            if (wr[c] > wl[c]) ln[c] = min(max(pred[c], wl[c]), wr[c] - 1u) >> 5;
         }
     }
 }
@@ -460,14 +456,14 @@ __device__ __forceinline__ void icount_learned(const SearchArgs& sa, uint32_t* s
                                                const uint32_t (&ae)[QPL], uint32_t (&cnt)[QPL],
                                                uint32_t (&fst)[QPL]) {
     constexpr int NC = 2 * QPL;
-    uint32_t x[NC], base[NC], len[NC], wl[NC], wr[NC], rlo[NC], rhi[NC], ln[NC];
+    uint32_t x[NC], base[NC], wl[NC], wr[NC], rlo[NC], rhi[NC];
     bool win[NC];
 #pragma unroll
     for (int q = 0; q < QPL; ++q) {
         x[2 * q] = ae[q] + 1u;
         x[2 * q + 1] = as[q];
     }
-    learned_windows<NC>(sa, scr, x, base, len, wl, wr, rlo, rhi, ln, win);
+    learned_windows<NC>(sa, scr, x, base, wl, wr, rlo, rhi, win);
     const uint32_t m = (sa.n + 31u) >> 5;     // heads in use
     uint32_t w[NC], pc[NC];
 #pragma unroll
@@ -1356,9 +1352,9 @@ __global__ void __launch_bounds__(256) k_rmi_window(SearchArgs sa, uint32_t whic
     for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const uint64_t i = t * blockDim.x + threadIdx.x;
         const uint32_t xi = i < n ? xs[i] : 0u;
-        uint32_t x[2] = {xi, xi}, base[2], len[2], wl[2], wr[2], rlo[2], rhi[2], ln[2];
+        uint32_t x[2] = {xi, xi}, base[2], wl[2], wr[2], rlo[2], rhi[2];
         bool win[2];
-        learned_windows<2>(sa, scr, x, base, len, wl, wr, rlo, rhi, ln, win);
+        learned_windows<2>(sa, scr, x, base, wl, wr, rlo, rhi, win);
         if (i < n) {
             lo[i] = win[which] ? wl[which] : base[which];
             hi[i] = win[which] ? wr[which] : base[which];
