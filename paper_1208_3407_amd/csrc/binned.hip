@@ -279,7 +279,9 @@ __device__ __forceinline__ uint32_t half16(const uint32_t* w, uint32_t j) {
 // in shuffle sb + s, counts them per region, writes the segment table of
 // (s, every region of k), and writes the records {start, end} in region
 // order to recs[s * na + table position range], either one by one (few
-// regions, or more than kStageRegions) or chunk by chunk through LDS.
+// regions, or more than kStageRegions) or chunk by chunk through LDS.  A
+// group that fits one chunk is placed only once: its chunk's region counts
+// are the segment table and the chunk is its final layout.
 // (8 waves per SIMD: two workgroups per CU, at most 64 VGPRs.)
 __global__ void __launch_bounds__(kBinThreads, 8) k_bin_place(
     BinGeom g, const uint2* __restrict__ packed, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ cursor,
@@ -311,6 +313,72 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_bin_place(
     const uint32_t ok = g.off[k], sh = g.shift, clen = g.off[k + 1] - g.off[k];
     const uint64_t gs = (sb + s) * na;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    if (g1 - g0 <= kStageRecs && nr <= kStageRegions) {
+        // The group fits one LDS chunk: every entry is placed once and ranked in its
+        // region, the counts give the segment table directly, and the chunk in region
+        // order is the group's final layout (written out sequentially).
+        const uint32_t nw2 = (nr + 1) >> 1;
+        const bool owner = threadIdx.x < nw2;
+        if (owner) cc[threadIdx.x] = 0u;
+        __syncthreads();
+        uint32_t st_[kStagePer], len_[kStagePer], key_[kStagePer];   // key = lr << 16 | rank, or ~0
+#pragma unroll
+        for (int u = 0; u < kStagePer; ++u) {
+            const uint32_t p = g0 + threadIdx.x + (uint32_t)u * blockDim.x;
+            const uint2 q = p < g1 ? packed[p] : make_uint2(0u, 0u);
+            key_[u] = 0xFFFFFFFFu;
+            st_[u] = 0u;
+            len_[u] = q.y;
+            if (!q.y) continue;
+            const uint32_t st = mc_place(gs + q.x, k0, k1, ok, clen - q.y + 1u);
+            const uint32_t lr = cr[(st - ok) >> sh];
+            if (lr >= nr) continue;
+            const uint32_t sft = 16u * (lr & 1u);
+            const uint32_t old = atomicAdd(&cc[lr >> 1], 1u << sft);
+            st_[u] = st;
+            key_[u] = (lr << 16) | ((old >> sft) & 0xFFFFu);
+        }
+        __syncthreads();
+        {
+            const uint32_t wv = owner ? cc[threadIdx.x] : 0u;
+            const uint32_t a0 = wv & 0xFFFFu, a1 = wv >> 16, tsum = a0 + a1;
+            const uint32_t lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+            const uint32_t x = wave_inclusive_scan<uint32_t>(tsum);
+            if (lane == kWave - 1) wsum[w] = x;
+            __syncthreads();
+            uint32_t pre = 0, tot = 0;
+            for (uint32_t j = 0; j < kBinThreads / kWave; ++j) {
+                if (j < w) pre += wsum[j];
+                tot += wsum[j];
+            }
+            pre += x - tsum;
+            if (owner) {
+                uint32_t* ss = seg_start + (uint64_t)s * nreg_max + rb;
+                uint32_t* sc = seg_cnt + (uint64_t)s * nreg_max + rb;
+                const uint32_t r0 = 2u * threadIdx.x, lo1 = pre + a0;
+                co[threadIdx.x] = pre | (lo1 << 16);
+                ss[r0] = g0 + pre;
+                sc[r0] = a0;
+                if (r0 + 1u < nr) {
+                    ss[r0 + 1u] = g0 + lo1;
+                    sc[r0 + 1u] = a1;
+                }
+            }
+            if (threadIdx.x == 0) staged_total = tot;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kStagePer; ++u) {
+            if (key_[u] == 0xFFFFFFFFu) continue;
+            const uint32_t lr = key_[u] >> 16;
+            stage[half16(co, lr) + (key_[u] & 0xFFFFu)] = make_uint2(st_[u], st_[u] + (len_[u] - 1u));
+        }
+        __syncthreads();
+        uint2* out = recs + (uint64_t)s * na + g0;
+        const uint32_t tot = staged_total;
+        for (uint32_t j = threadIdx.x; j < tot; j += blockDim.x) out[j] = stage[j];
+        return;
+    }
     for (uint32_t p0 = g0 + threadIdx.x; p0 < g1; p0 += ILP * blockDim.x) {
         uint2 q[ILP];
 #pragma unroll
