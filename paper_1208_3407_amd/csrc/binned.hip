@@ -268,6 +268,9 @@ constexpr uint32_t kStageRegions = 2048;
 constexpr uint32_t kStageMinRegions = 128;
 constexpr uint32_t kStageRecs = 5632;      // 44 KB
 constexpr int kStagePer = (kStageRecs + kBinThreads - 1) / kBinThreads;
+static_assert(kStageRegions <= 2 * kBinThreads, "one thread owns two regions' chunk counters");
+static_assert(kStageRecs < (1u << 16), "chunk counts and offsets are 16-bit");
+static_assert(kMaxCells <= (1u << 16), "cell-to-region table entries are 16-bit");
 
 // Entry j of an array of 16-bit values packed two per word.
 __device__ __forceinline__ uint32_t half16(const uint32_t* w, uint32_t j) {
@@ -795,7 +798,8 @@ hipError_t launch_bin_batch(const uint32_t* chrom_len, uint32_t n_chrom, const M
                            reinterpret_cast<const RegionDesc*>(w.desc), w.offsets + ncells, w.seg_start, w.seg_cnt,
                            w.nreg_max, nb, reinterpret_cast<const uint2*>(w.recs), na, 1u, w.partial);
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
-    const uint32_t gy = (uint32_t)std::min<uint64_t>(std::max<uint64_t>((uint64_t)w.nreg_max * w.splits / 64, 1), 256);
+    // about 8 region shares per thread, at most 512 partial sums per shuffle into the atomics
+    const uint32_t gy = (uint32_t)std::min<uint64_t>(std::max<uint64_t>((uint64_t)w.nreg_max * w.splits / 8, 1), 512);
     hipLaunchKernelGGL(k_bin_reduce, dim3((nb + 255) / 256, gy), dim3(256), 0, s, w.partial, w.offsets + ncells,
                        w.splits, nb, totals);
     if ((e = hipGetLastError()) != hipSuccess) return e;
