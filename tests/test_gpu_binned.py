@@ -136,6 +136,23 @@ def test_binned_bucket_edges():
     check(L, a_s, a_e, b_s, b_e, 13, 0, 24, 8)
 
 
+@pytest.mark.parametrize("n_b", [100_000, 800_000])
+@pytest.mark.parametrize("na", [5631, 5632, 5633, 11264, 11265])
+def test_binned_group_sizes_around_one_chunk(n_b, na):
+    """One 40 Mbp chromosome, so that each (shuffle, chromosome) group holds all na
+    queries: groups of up to 5632 queries are placed once and written as one LDS chunk;
+    one more query sends the group through the counting sweep and then two chunks (about
+    200 regions, staged) or the one-by-one writes (about 25 regions)."""
+    note("case: binned group of %d queries, n_b=%d" % (na, n_b))
+    r = np.random.default_rng(na + n_b)
+    L = np.array([40_000_000], np.uint32)
+    b_s = r.integers(0, 39_990_000, n_b).astype(np.uint32)
+    b_e = b_s + r.integers(0, 3000, n_b).astype(np.uint32)
+    a_s = r.integers(0, 39_900_000, na).astype(np.uint32)
+    a_e = a_s + r.integers(0, 20_000, na).astype(np.uint32)
+    check(L, a_s, a_e, b_s, b_e, 17, 1, 8, 3)
+
+
 def test_binned_oversize_region_and_empty_chromosomes():
     """Empty chromosomes between non-empty ones, 12,000 intervals of B on one
     coordinate (a region too large for LDS, searched in HBM), B keys past the
