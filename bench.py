@@ -249,9 +249,10 @@ def batch_model_bytes(na_list, nb_list):
     return total
 
 
-def other_configs(bits, dev, timed, train):
-    """The other workloads, each on its own data: small single-chromosome counts, genome-scale
-    counts, the small-reference Monte-Carlo and the uneven batch of pairs."""
+def other_configs(bits, dev, timed, train, which=("c0", "c1", "c2", "c3")):
+    """The other workloads, each on its own data: small single-chromosome counts (c0), genome-scale
+    counts (c1), the small-reference Monte-Carlo (c2) and the uneven batch of pairs (c3); `which`
+    names the ones to run."""
     import torch
 
     from paper_1208_3407_amd import datagen
@@ -263,7 +264,19 @@ def other_configs(bits, dev, timed, train):
         return bits.bits_project(lengths, up(S.chrom), up(S.start), up(S.end))
 
     out = {}
-    # 10k x 10k on one 10 Mbp chromosome: launch-latency bound
+    if "c0" in which:
+        out["c0"] = config_c0(bits, datagen, proj, timed, train)
+    if "c1" in which:
+        out["c1"] = config_c1(bits, datagen, proj, timed, train, dev)
+    if "c2" in which:
+        out["c2"] = config_c2(bits, datagen, proj, timed, train, dev)
+    if "c3" in which:
+        out["c3"] = config_c3(bits, datagen, proj, timed, train)
+    return out
+
+
+def config_c0(bits, datagen, proj, timed, train):
+    """10k x 10k on one 10 Mbp chromosome: launch-latency bound."""
     lengths, A, B = datagen.w0_sets()
     a_s, a_e = proj(lengths, A)
     b_s, b_e = proj(lengths, B)
@@ -274,10 +287,13 @@ def other_configs(bits, dev, timed, train):
         t = timed(lambda: bits.bits_count_per_query(ref, a_s, a_e, launch={"path": path}), reps=5)
         c0[name + "_ms"] = t
         c0[name + "_aps"] = len(A.start) / (t / 1e3)
-    out["c0"] = c0
-    del ref
+    return c0
 
-    # 1e7 x 1e7 on the 24-chromosome genome
+
+def config_c1(bits, datagen, proj, timed, train, dev):
+    """1e7 x 1e7 on the 24-chromosome genome, each path at its autotuned launch."""
+    import torch
+
     lengths, A, B = datagen.w1_sets()
     a_s, a_e = proj(lengths, A)
     b_s, b_e = proj(lengths, B)
@@ -297,10 +313,13 @@ def other_configs(bits, dev, timed, train):
         c1[name + "_aps"] = len(A.start) / (t / 1e3)
         c1[name + "_launch"] = lp
     c1["paths_equal"] = len(set(totals.values())) == 1
-    out["c1"] = c1
-    del ref, ws, counts
+    return c1
 
-    # Monte-Carlo: 1e5 queries x 10,000 shuffles against 1e6
+
+def config_c2(bits, datagen, proj, timed, train, dev):
+    """Monte-Carlo: 1e5 queries x 10,000 shuffles against 1e6, binned and query-ordered."""
+    import torch
+
     lengths, A, B = datagen.w2_sets()
     a_s, a_e = proj(lengths, A)
     b_s, b_e = proj(lengths, B)
@@ -312,15 +331,18 @@ def other_configs(bits, dev, timed, train):
                                                                    batch=MC_BATCH, workspace=bws)), reps=2)
     t_q = timed(lambda: res.__setitem__("q", bits.bits_mc_pvalue(ref, a_s, a_e, lengths, MC_SEED, 0, N,
                                                                  launch=RECORDED_MC)), reps=1)
-    out["c2"] = {"workload": "Monte-Carlo 1e5 queries x 10,000 shuffles against 1e6",
+    return {"workload": "Monte-Carlo 1e5 queries x 10,000 shuffles against 1e6",
                  "binned_ms": t_bin, "binned_shuffles_per_s": N / (t_bin / 1e3),
                  "binned_aps": N * len(A.start) / (t_bin / 1e3),
                  "query_ordered_learned_ms": t_q, "query_ordered_shuffles_per_s": N / (t_q / 1e3),
                  "totals_equal": bool(torch.equal(res["b"].totals, res["q"].totals)),
                  "p_upper": bits.bits_pvalue(int(res["b"].n_ge.item()), N)}
-    del ref, bws, res
 
-    # the uneven batch: 32 query sets x 64 references, one graph-captured persistent launch
+
+def config_c3(bits, datagen, proj, timed, train):
+    """The uneven batch: 32 query sets x 64 references, one graph-captured persistent launch."""
+    import torch
+
     lengths, Q, R = datagen.w3_sets()
     qd = [proj(lengths, S) for S in Q]
     rd = [proj(lengths, S) for S in R]
@@ -348,9 +370,7 @@ def other_configs(bits, dev, timed, train):
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                             "model_bytes": mb, "traffic": None,
                             "model": "8 B query read + 2 x (h_mid + 1) x 128 B per (query, reference)"}
-    out["c3"] = c3
-    del refs, qd, rd, res
-    return out
+    return c3
 
 
 def main():
@@ -360,6 +380,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the other workloads (outside the timed step)")
+    ap.add_argument("--configs", default="c0,c1,c2,c3",
+                    help="the other workloads to run, comma-separated (c0 small counts, c1 genome-scale counts, "
+                         "c2 small-reference Monte-Carlo, c3 uneven batch)")
     ap.add_argument("--epochs", type=int, default=TRAIN_EPOCHS)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the recorded best launch shapes instead of timing candidates")
@@ -615,7 +638,8 @@ def main():
     other = "k_bin_search" if dom == "k_bin_place" else "k_bin_place"
     learned_achieved = BYTES_PER_EVAL_LEARNED * N_SHUF * N_MC / (t_mc_learned / 1e3) / 1e9
 
-    configs = None if args.no_configs else other_configs(bits, dev, timed, train)
+    which = [] if args.no_configs else [c for c in args.configs.split(",") if c]
+    configs = other_configs(bits, dev, timed, train, which) if which else None
 
     result = {
         "metric": "A-intervals counted/s (learned vs binary-search index); MC shuffles/s",
