@@ -389,6 +389,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with a plain 1 GiB device copy (HBM byte-counter calibration)")
     args = ap.parse_args()
+    which = [] if args.no_configs else [c for c in args.configs.split(",") if c]
+    unknown = sorted(set(which) - {"c0", "c1", "c2", "c3"})
+    if unknown:
+        raise SystemExit("bench.py: unknown --configs entries %s (known: c0, c1, c2, c3)" % ", ".join(unknown))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (one process on one GPU); "
               "run with --gpus 1", file=sys.stderr)
@@ -638,7 +642,6 @@ def main():
     other = "k_bin_search" if dom == "k_bin_place" else "k_bin_place"
     learned_achieved = BYTES_PER_EVAL_LEARNED * N_SHUF * N_MC / (t_mc_learned / 1e3) / 1e9
 
-    which = [] if args.no_configs else [c for c in args.configs.split(",") if c]
     configs = other_configs(bits, dev, timed, train, which) if which else None
 
     result = {
